@@ -1,0 +1,131 @@
+/*
+ * ntt_mi355x.h -- C ABI of the batched negacyclic NTT library for MI355X (gfx950).
+ *
+ * Paper: Kim, Jung, Park, Ahn, "Accelerating Number Theoretic Transformations for
+ * Bootstrappable Homomorphic Encryption on GPUs", arXiv 2012.01968.
+ *
+ * Problem statement (Section III-B; Algorithm 1, its REQUIRE and ENSURE clauses):
+ * a polynomial of Z_Q[X]/(X^N+1) is held in RNS form as L residue vectors of length
+ * N, vector l taken mod a prime q_l = 1 (mod 2N).  The library applies the merged-twist
+ * NTT (Section III-A) to every vector of a batch, its inverse, the element-wise
+ * product in the NTT domain, and the full negacyclic product.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Data layout   A batch is a device array of uint64_t laid out [n_polys][L][N]
+ *               (limb-major, each limb vector contiguous).  Vector (p, l) starts at
+ *               element (p*L + l)*N and is reduced mod q_l.
+ * Values        Inputs must be canonical residues in [0, q_l); outputs are canonical.
+ * Order         Forward output and inverse input are in bit-reversed order: slot i of
+ *               the forward output holds A_{brv(i)} = sum_n a_n psi^{n(2 brv(i)+1)},
+ *               exactly what Algorithm 1 leaves in place.  Inverse output and polymul
+ *               inputs/outputs are coefficients in natural order.
+ * Root          psi_l is the smallest primitive 2N-th root of unity mod q_l (the paper
+ *               does not fix one; ntt_plan_get_roots reports the roots in use).
+ * Streams       `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *               Calls enqueue work on it and return at once; results are ready when
+ *               the stream reaches that point.
+ * Memory        The caller owns every data buffer.  The plan owns its device tables.
+ *               Device pointers must be 16-byte aligned.
+ * Errors        Argument errors are reported synchronously and nothing is enqueued.
+ *               A failed launch returns NTT_ERR_HIP; faults that happen on the device
+ *               surface at the caller's next synchronisation with the stream.
+ *               No C++ exception crosses this interface.
+ * Threads       A plan is immutable after creation and may be used from any host
+ *               thread and stream at once, except that ntt_polymul_negacyclic uses
+ *               plan-owned scratch and serialises on an internal lock.
+ */
+#ifndef NTT_MI355X_H
+#define NTT_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ntt_plan_s* ntt_plan_t;
+
+typedef enum {
+    NTT_OK = 0,
+    NTT_ERR_ARG = -1,          /* null pointer, zero count, bad option value       */
+    NTT_ERR_N = -2,            /* N not a power of two in [2, 2^17]                */
+    NTT_ERR_PRIME = -3,        /* a modulus is not prime, not 1 mod 2N, not below  */
+                               /* 2^62, or repeated                                */
+    NTT_ERR_NOMEM = -4,        /* host or device allocation failed                 */
+    NTT_ERR_HIP = -5,          /* a HIP runtime call or kernel launch failed       */
+    NTT_ERR_UNSUPPORTED = -6   /* option combination not built into the library    */
+} ntt_status;
+
+/* Twiddle sources (Section VII).  TABLE reads every twiddle and its Shoup companion
+ * from a precomputed table; OT ("on-the-fly twiddling") rebuilds the twiddles of the
+ * last `ot_stages` forward stages (first inverse stages) from two small base tables by
+ * multiplying the operand by both factors in turn. */
+enum { NTT_TWIDDLE_AUTO = 0, NTT_TWIDDLE_TABLE = 1, NTT_TWIDDLE_OT = 2 };
+
+/* Plan options.  A zero-filled struct (or NULL) asks for the defaults. */
+typedef struct {
+    int32_t twiddle_mode;   /* NTT_TWIDDLE_*; AUTO picks TABLE unless ot_stages > 0     */
+    int32_t ot_stages;      /* 1 or 2: stages rebuilt on the fly (OT mode); 0 = 2       */
+    int32_t ot_log2_base;   /* log2 of the OT digit base; 0 = 10 (base 1024)            */
+    int32_t log2_n1;        /* size of the first (column) pass, N = N1 * N2; 0 = auto;  */
+                            /* -1 forces the single-pass kernel where N allows it       */
+    int32_t reserved[4];    /* must be zero                                             */
+} ntt_plan_opts;
+
+/* Create a plan for length-N transforms over L primes (Section III-B; Algorithm 1
+ * REQUIRE: each q = 1 mod 2N).  `primes` is a host array of L distinct primes with
+ * 2 < q < 2^62 and q = 1 (mod 2N).  The plan computes psi_l, the twiddle tables
+ * Psi[i] = psi^{brv(i)} and Psi_inv[i] = psi^{-brv(i)} with their Shoup companions
+ * floor(w * 2^64 / q) (Algorithm 4), N^{-1}, and the OT base tables, and uploads
+ * them to the current HIP device.  On success *out holds the plan; on failure *out
+ * is set to NULL.  Errors: NTT_ERR_ARG, NTT_ERR_N, NTT_ERR_PRIME, NTT_ERR_NOMEM,
+ * NTT_ERR_HIP. */
+ntt_status ntt_plan_create(ntt_plan_t* out, uint32_t N, const uint64_t* primes, uint32_t L,
+                           const ntt_plan_opts* opts);
+
+/* Release a plan and its device memory.  The caller must make sure no enqueued
+ * work still uses it (synchronise the streams first).  NULL is accepted. */
+ntt_status ntt_plan_destroy(ntt_plan_t plan);
+
+/* Copy the L roots psi_l in use into the host array psi_out (L entries). */
+ntt_status ntt_plan_get_roots(ntt_plan_t plan, uint64_t* psi_out);
+
+/* N, L and the pass split chosen by the plan (any pointer may be NULL). */
+ntt_status ntt_plan_get_info(ntt_plan_t plan, uint32_t* N, uint32_t* L, uint32_t* log2_n1,
+                             int32_t* twiddle_mode, int32_t* ot_stages);
+
+/* In-place forward NTT of every vector of d_data ([n_polys][L][N] uint64, device).
+ * Section III-A merged-twist transform computed as Algorithm 1 (Cooley-Tukey with the
+ * butterfly of Algorithm 2 and Shoup's modmul of Algorithm 4) split into an LDS-staged
+ * column pass and row pass (Section VI-C).  Output in bit-reversed order. */
+ntt_status ntt_forward(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, void* stream);
+
+/* In-place inverse: takes bit-reversed NTT-domain vectors and returns natural-order
+ * coefficients, with the Psi^{-1} twist and the 1/N scale merged in (Section III-A). */
+ntt_status ntt_inverse(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, void* stream);
+
+/* Element-wise product in the NTT domain (Section III-A, the Hadamard product):
+ * d_c[k] = d_a[k] * d_b[k] mod q_l for every element of the [n_polys][L][N] batch.
+ * d_c may alias d_a or d_b. */
+ntt_status ntt_pointwise_mul(ntt_plan_t plan, const uint64_t* d_a, const uint64_t* d_b, uint64_t* d_c,
+                             uint32_t n_polys, void* stream);
+
+/* Negacyclic product in Z_q[X]/(X^N+1) per vector (Section III-A):
+ * c = iNTT(NTT(a) * NTT(b)).  Inputs and output are natural-order coefficients;
+ * d_a and d_b are left unchanged; d_c may alias d_a but not d_b.  Uses a plan-owned
+ * scratch buffer of n_polys*L*N*8 bytes, grown on demand. */
+ntt_status ntt_polymul_negacyclic(ntt_plan_t plan, const uint64_t* d_a, const uint64_t* d_b, uint64_t* d_c,
+                                  uint32_t n_polys, void* stream);
+
+/* Human-readable name of a status code (static storage). */
+const char* ntt_status_string(ntt_status s);
+
+/* Message of the last failure on the calling thread (static per-thread storage). */
+const char* ntt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NTT_MI355X_H */

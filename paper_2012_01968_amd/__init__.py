@@ -1,0 +1,172 @@
+"""Batched negacyclic NTT for MI355X (gfx950): Python binding of libntt_mi355x.so.
+
+Every function here marshals arguments for the C entry point of the same name
+(include/ntt_mi355x.h); all arithmetic runs in the HIP kernels.  Device buffers may be
+given as torch tensors (int64 or uint64, on the GPU; their storage is read as uint64)
+or as raw integer device addresses.  Streams may be torch streams, raw hipStream_t
+integers, or None for torch's current stream.
+
+Loading fails loudly (ImportError) when the built library is missing: there is no
+fallback path.  Build it with ``python -m paper_2012_01968_amd.build``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = [
+    "NttError", "Plan", "ntt_plan_create", "ntt_plan_destroy", "ntt_plan_get_roots", "ntt_plan_get_info",
+    "ntt_forward", "ntt_inverse", "ntt_pointwise_mul", "ntt_polymul_negacyclic", "ntt_status_string",
+    "library_path", "TWIDDLE_AUTO", "TWIDDLE_TABLE", "TWIDDLE_OT",
+]
+
+TWIDDLE_AUTO, TWIDDLE_TABLE, TWIDDLE_OT = 0, 1, 2
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libntt_mi355x.so")
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+if not os.path.exists(_LIB_PATH):
+    raise ImportError(f"{_LIB_PATH} is not built; run `python -m paper_2012_01968_amd.build`")
+
+_lib = ctypes.CDLL(_LIB_PATH)
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("twiddle_mode", ctypes.c_int32), ("ot_stages", ctypes.c_int32),
+                ("ot_log2_base", ctypes.c_int32), ("log2_n1", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+_vp = ctypes.c_void_p
+_u32 = ctypes.c_uint32
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_lib.ntt_plan_create.argtypes = [ctypes.POINTER(_vp), _u32, _u64p, _u32, ctypes.POINTER(_Opts)]
+_lib.ntt_plan_destroy.argtypes = [_vp]
+_lib.ntt_plan_get_roots.argtypes = [_vp, _u64p]
+_lib.ntt_plan_get_info.argtypes = [_vp, ctypes.POINTER(_u32), ctypes.POINTER(_u32), ctypes.POINTER(_u32),
+                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+_lib.ntt_forward.argtypes = [_vp, _vp, _u32, _vp]
+_lib.ntt_inverse.argtypes = [_vp, _vp, _u32, _vp]
+_lib.ntt_pointwise_mul.argtypes = [_vp, _vp, _vp, _vp, _u32, _vp]
+_lib.ntt_polymul_negacyclic.argtypes = [_vp, _vp, _vp, _vp, _u32, _vp]
+_lib.ntt_status_string.argtypes = [ctypes.c_int]
+_lib.ntt_status_string.restype = ctypes.c_char_p
+_lib.ntt_last_error.argtypes = []
+_lib.ntt_last_error.restype = ctypes.c_char_p
+for _f in ("ntt_plan_create", "ntt_plan_destroy", "ntt_plan_get_roots", "ntt_plan_get_info", "ntt_forward",
+           "ntt_inverse", "ntt_pointwise_mul", "ntt_polymul_negacyclic"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+
+class NttError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.ntt_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {ntt_status_string(status)}: {msg}")
+
+
+def _check(status: int, where: str) -> None:
+    if status != 0:
+        raise NttError(status, where)
+
+
+def ntt_status_string(status: int) -> str:
+    return _lib.ntt_status_string(status).decode()
+
+
+class Plan:
+    """Owns an ntt_plan_t; destroyed explicitly or when garbage-collected."""
+
+    def __init__(self, handle: int, N: int, L: int):
+        self.handle = handle
+        self.N = N
+        self.L = L
+
+    def destroy(self) -> None:
+        if self.handle:
+            _check(_lib.ntt_plan_destroy(self.handle), "ntt_plan_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def _addr(buf) -> int:
+    if buf is None:
+        raise ValueError("buffer is None")
+    if isinstance(buf, int):
+        return buf
+    return int(buf.data_ptr())
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream) or None
+    if isinstance(stream, int):
+        return stream or None
+    return int(stream.cuda_stream) or None
+
+
+def _polys(plan: Plan, buf, n_polys) -> int:
+    if n_polys is not None:
+        return int(n_polys)
+    numel = buf.numel()
+    per = plan.N * plan.L
+    if numel % per:
+        raise ValueError(f"buffer of {numel} elements is not a whole number of [L][N] polynomials")
+    return numel // per
+
+
+def ntt_plan_create(N: int, primes, *, twiddle_mode: int = 0, ot_stages: int = 0, ot_log2_base: int = 0,
+                    log2_n1: int = 0) -> Plan:
+    primes = [int(q) for q in primes]
+    arr = (ctypes.c_uint64 * len(primes))(*primes)
+    opts = _Opts(twiddle_mode, ot_stages, ot_log2_base, log2_n1)
+    h = _vp()
+    _check(_lib.ntt_plan_create(ctypes.byref(h), N, arr, len(primes), ctypes.byref(opts)), "ntt_plan_create")
+    return Plan(h.value, N, len(primes))
+
+
+def ntt_plan_destroy(plan: Plan) -> None:
+    plan.destroy()
+
+
+def ntt_plan_get_roots(plan: Plan) -> list[int]:
+    out = (ctypes.c_uint64 * plan.L)()
+    _check(_lib.ntt_plan_get_roots(plan.handle, out), "ntt_plan_get_roots")
+    return list(out)
+
+
+def ntt_plan_get_info(plan: Plan) -> dict:
+    N, L, n1 = _u32(), _u32(), _u32()
+    mode, ots = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.ntt_plan_get_info(plan.handle, ctypes.byref(N), ctypes.byref(L), ctypes.byref(n1),
+                                  ctypes.byref(mode), ctypes.byref(ots)), "ntt_plan_get_info")
+    return {"N": N.value, "L": L.value, "log2_n1": n1.value, "twiddle_mode": mode.value, "ot_stages": ots.value}
+
+
+def ntt_forward(plan: Plan, data, n_polys: int | None = None, stream=None) -> None:
+    _check(_lib.ntt_forward(plan.handle, _addr(data), _polys(plan, data, n_polys), _stream(stream)), "ntt_forward")
+
+
+def ntt_inverse(plan: Plan, data, n_polys: int | None = None, stream=None) -> None:
+    _check(_lib.ntt_inverse(plan.handle, _addr(data), _polys(plan, data, n_polys), _stream(stream)), "ntt_inverse")
+
+
+def ntt_pointwise_mul(plan: Plan, a, b, c, n_polys: int | None = None, stream=None) -> None:
+    _check(_lib.ntt_pointwise_mul(plan.handle, _addr(a), _addr(b), _addr(c), _polys(plan, a, n_polys),
+                                  _stream(stream)), "ntt_pointwise_mul")
+
+
+def ntt_polymul_negacyclic(plan: Plan, a, b, c, n_polys: int | None = None, stream=None) -> None:
+    _check(_lib.ntt_polymul_negacyclic(plan.handle, _addr(a), _addr(b), _addr(c), _polys(plan, a, n_polys),
+                                       _stream(stream)), "ntt_polymul_negacyclic")

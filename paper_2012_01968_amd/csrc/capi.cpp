@@ -1,0 +1,422 @@
+// C ABI of the NTT library: plan construction and the batched entry points.
+// Every entry point catches everything; no exception crosses the interface.
+#include "ntt_mi355x.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "kernels.hpp"
+#include "passes.hpp"
+#include "plan_math.hpp"
+
+using nttk::PassArgs;
+using nttk::Tw;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ntt_status fail(ntt_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+ntt_status hip_fail(hipError_t e, const char* where) {
+  return fail(NTT_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// Makes the plan's device current for the duration of a call and restores the
+// caller's device afterwards.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) {
+      ok = false;
+      return;
+    }
+    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+template <typename T>
+hipError_t upload(T** dst, const std::vector<T>& src) {
+  *dst = nullptr;
+  if (src.empty()) return hipSuccess;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), src.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+}  // namespace
+
+struct ntt_plan_s {
+  uint32_t N = 0, logN = 0, L = 0, logN1 = 0;
+  int32_t twiddle_mode = NTT_TWIDDLE_TABLE;
+  int32_t ot_stages = 0;
+  uint32_t ot_log2_base = 10;
+  int device = 0;
+  std::vector<uint64_t> primes, psis;
+
+  uint64_t* d_q = nullptr;
+  Tw* d_tw_fwd = nullptr;
+  Tw* d_tw_inv = nullptr;
+  Tw* d_ot_lo_fwd = nullptr;
+  Tw* d_ot_hi_fwd = nullptr;
+  Tw* d_ot_lo_inv = nullptr;
+  Tw* d_ot_hi_inv = nullptr;
+  Tw* d_scale = nullptr;
+  uint64_t* d_mu = nullptr;
+  uint32_t* d_bits = nullptr;
+
+  // polymul scratch: one buffer, ordered across streams by an event
+  std::mutex scratch_mu;
+  uint64_t* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  hipEvent_t scratch_ev = nullptr;
+  bool scratch_pending = false;
+
+  ~ntt_plan_s() {
+    if (scratch_ev) {
+      (void)hipEventSynchronize(scratch_ev);
+      (void)hipEventDestroy(scratch_ev);
+    }
+    void* ptrs[] = {d_q, d_tw_fwd, d_tw_inv, d_ot_lo_fwd, d_ot_hi_fwd, d_ot_lo_inv, d_ot_hi_inv,
+                    d_scale, d_mu, d_bits, scratch};
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+  }
+
+  PassArgs args(uint64_t* data, uint32_t n_polys, bool inverse) const {
+    PassArgs a{};
+    a.data = data;
+    a.tw = inverse ? d_tw_inv : d_tw_fwd;
+    a.ot_lo = inverse ? d_ot_lo_inv : d_ot_lo_fwd;
+    a.ot_hi = inverse ? d_ot_hi_inv : d_ot_hi_fwd;
+    a.q = d_q;
+    a.scale = d_scale;
+    a.n_vec = (uint64_t)n_polys * L;
+    a.L = L;
+    a.logN = logN;
+    a.logN1 = logN1;
+    a.ot_log2_base = ot_log2_base;
+    return a;
+  }
+  int active_ot() const { return twiddle_mode == NTT_TWIDDLE_OT ? ot_stages : 0; }
+};
+
+static ntt_status build_plan(ntt_plan_s* p, uint32_t N, const uint64_t* primes, uint32_t L,
+                             const ntt_plan_opts* opts) {
+  if (N < 2 || N > (1u << 17) || (N & (N - 1))) return fail(NTT_ERR_N, "N must be a power of two in [2, 2^17]");
+  p->N = N;
+  p->logN = 0;
+  while ((1u << p->logN) < N) ++p->logN;
+  p->L = L;
+
+  ntt_plan_opts o{};
+  if (opts) o = *opts;
+  for (int32_t r : o.reserved)
+    if (r != 0) return fail(NTT_ERR_ARG, "reserved option fields must be zero");
+  if (o.twiddle_mode < 0 || o.twiddle_mode > 2) return fail(NTT_ERR_ARG, "twiddle_mode out of range");
+  if (o.ot_stages < 0 || o.ot_stages > 2) return fail(NTT_ERR_ARG, "ot_stages must be 0, 1 or 2");
+  if (o.ot_log2_base < 0 || o.ot_log2_base > 16) return fail(NTT_ERR_ARG, "ot_log2_base out of range");
+  int mode = o.twiddle_mode;
+  if (mode == NTT_TWIDDLE_AUTO) mode = o.ot_stages > 0 ? NTT_TWIDDLE_OT : NTT_TWIDDLE_TABLE;
+  p->twiddle_mode = mode;
+  p->ot_stages = mode == NTT_TWIDDLE_OT ? (o.ot_stages ? o.ot_stages : 2) : 0;
+  p->ot_log2_base = o.ot_log2_base ? (uint32_t)o.ot_log2_base : 10u;
+  if (mode == NTT_TWIDDLE_OT && p->ot_log2_base >= p->logN)
+    return fail(NTT_ERR_UNSUPPORTED, "OT needs a digit base below N");
+
+  if (o.log2_n1 == 0) {
+    p->logN1 = p->logN <= 12 ? 0 : p->logN / 2;
+  } else if (o.log2_n1 < 0) {
+    p->logN1 = 0;
+  } else {
+    p->logN1 = (uint32_t)o.log2_n1;
+  }
+  if (!nttk::shape_supported(p->logN, p->logN1, p->active_ot()))
+    return fail(NTT_ERR_UNSUPPORTED, "no kernels for this (N, N1, OT stages) combination");
+
+  // ---- primes
+  p->primes.assign(primes, primes + L);
+  {
+    std::vector<uint64_t> sorted(p->primes);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+      return fail(NTT_ERR_PRIME, "primes must be distinct");
+  }
+  for (uint32_t l = 0; l < L; ++l) {
+    const uint64_t q = p->primes[l];
+    if (q <= 2 || q >= (1ull << 62)) return fail(NTT_ERR_PRIME, "prime " + std::to_string(q) + " not in (2, 2^62)");
+    if ((q - 1) % (2ull * N)) return fail(NTT_ERR_PRIME, "prime " + std::to_string(q) + " is not 1 mod 2N");
+    if (!nttp::is_prime(q)) return fail(NTT_ERR_PRIME, std::to_string(q) + " is not prime");
+  }
+
+  // ---- tables (host), one worker per block of limbs
+  const size_t NN = N;
+  const uint32_t b = p->ot_log2_base;
+  const bool want_ot = b < p->logN;
+  const size_t B = want_ot ? (size_t)1 << b : 0, H = want_ot ? NN >> b : 0;
+  std::vector<Tw> tw_fwd(L * NN), tw_inv(L * NN), ot_lo_f(L * B), ot_hi_f(L * H), ot_lo_i(L * B), ot_hi_i(L * H),
+      scale(2 * (size_t)L);
+  std::vector<uint64_t> mu(L), psis(L);
+  std::vector<uint32_t> bits(L);
+  std::vector<int> bad(L, 0);
+
+  auto work = [&](uint32_t l0, uint32_t l1) {
+    std::vector<uint64_t> pw(NN), pwi(NN);
+    for (uint32_t l = l0; l < l1; ++l) {
+      const uint64_t q = p->primes[l];
+      const uint64_t psi = nttp::smallest_primitive_root(q, N);
+      if (!psi) {
+        bad[l] = 1;
+        continue;
+      }
+      psis[l] = psi;
+      const uint64_t psi_inv = nttp::powmod(psi, q - 2, q);
+      pw[0] = pwi[0] = 1;
+      for (size_t e = 1; e < NN; ++e) {
+        pw[e] = nttp::mulmod(pw[e - 1], psi, q);
+        pwi[e] = nttp::mulmod(pwi[e - 1], psi_inv, q);
+      }
+      Tw* tf = &tw_fwd[l * NN];
+      Tw* ti = &tw_inv[l * NN];
+      for (size_t i = 0; i < NN; ++i) {
+        const uint32_t e = nttp::bitrev((uint32_t)i, (int)p->logN);
+        tf[i] = Tw{pw[e], nttp::shoup_companion(pw[e], q)};
+        ti[i] = Tw{pwi[e], nttp::shoup_companion(pwi[e], q)};
+      }
+      for (size_t k = 0; k < B; ++k) {
+        ot_lo_f[l * B + k] = Tw{pw[k], nttp::shoup_companion(pw[k], q)};
+        ot_lo_i[l * B + k] = Tw{pwi[k], nttp::shoup_companion(pwi[k], q)};
+      }
+      for (size_t h = 0; h < H; ++h) {
+        const uint64_t wf = pw[h << b], wi = pwi[h << b];
+        ot_hi_f[l * H + h] = Tw{wf, nttp::shoup_companion(wf, q)};
+        ot_hi_i[l * H + h] = Tw{wi, nttp::shoup_companion(wi, q)};
+      }
+      const uint64_t n_inv = nttp::powmod(N % q, q - 2, q);
+      const uint64_t w1n = nttp::mulmod(ti[N > 1 ? 1 : 0].w, n_inv, q);
+      scale[2 * l] = Tw{n_inv, nttp::shoup_companion(n_inv, q)};
+      scale[2 * l + 1] = Tw{w1n, nttp::shoup_companion(w1n, q)};
+      uint32_t s = 0;
+      while (s < 64 && (q >> s)) ++s;
+      bits[l] = s;
+      mu[l] = (uint64_t)(((nttp::u128)1 << (2 * s)) / q);
+    }
+  };
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const uint32_t workers = (uint64_t)L * NN >= (1u << 18) ? std::min<uint32_t>(hw, L) : 1u;
+  if (workers <= 1) {
+    work(0, L);
+  } else {
+    std::vector<std::thread> th;
+    for (uint32_t w = 0; w < workers; ++w)
+      th.emplace_back(work, (uint32_t)((uint64_t)L * w / workers), (uint32_t)((uint64_t)L * (w + 1) / workers));
+    for (auto& t : th) t.join();
+  }
+  for (uint32_t l = 0; l < L; ++l)
+    if (bad[l]) return fail(NTT_ERR_PRIME, "no primitive 2N-th root found mod " + std::to_string(p->primes[l]));
+  p->psis = psis;
+
+  if (hipGetDevice(&p->device) != hipSuccess) return fail(NTT_ERR_HIP, "hipGetDevice failed");
+  hipError_t e;
+  if ((e = upload(&p->d_q, p->primes)) != hipSuccess || (e = upload(&p->d_tw_fwd, tw_fwd)) != hipSuccess ||
+      (e = upload(&p->d_tw_inv, tw_inv)) != hipSuccess || (e = upload(&p->d_ot_lo_fwd, ot_lo_f)) != hipSuccess ||
+      (e = upload(&p->d_ot_hi_fwd, ot_hi_f)) != hipSuccess || (e = upload(&p->d_ot_lo_inv, ot_lo_i)) != hipSuccess ||
+      (e = upload(&p->d_ot_hi_inv, ot_hi_i)) != hipSuccess || (e = upload(&p->d_scale, scale)) != hipSuccess ||
+      (e = upload(&p->d_mu, mu)) != hipSuccess || (e = upload(&p->d_bits, bits)) != hipSuccess) {
+    if (e == hipErrorOutOfMemory) return fail(NTT_ERR_NOMEM, "device allocation of plan tables failed");
+    return hip_fail(e, "uploading plan tables");
+  }
+  if ((e = hipEventCreateWithFlags(&p->scratch_ev, hipEventDisableTiming)) != hipSuccess)
+    return hip_fail(e, "hipEventCreate");
+  return NTT_OK;
+}
+
+static ntt_status check_data(ntt_plan_t plan, const void* ptr, uint32_t n_polys) {
+  if (!plan) return fail(NTT_ERR_ARG, "plan is NULL");
+  if (!ptr) return fail(NTT_ERR_ARG, "data pointer is NULL");
+  if (reinterpret_cast<uintptr_t>(ptr) & 15) return fail(NTT_ERR_ARG, "data pointer must be 16-byte aligned");
+  if (n_polys == 0) return fail(NTT_ERR_ARG, "n_polys must be at least 1");
+  // every pass launches at most N/16 + 1 workgroups per vector; keep the grid below 2^31
+  const uint64_t n_vec = (uint64_t)n_polys * plan->L;
+  if (n_vec * ((uint64_t)plan->N / 16 + 1) >= (1ull << 31)) return fail(NTT_ERR_ARG, "batch too large for one launch");
+  return NTT_OK;
+}
+
+extern "C" {
+
+ntt_status ntt_plan_create(ntt_plan_t* out, uint32_t N, const uint64_t* primes, uint32_t L,
+                           const ntt_plan_opts* opts) {
+  try {
+    if (!out) return fail(NTT_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!primes || L == 0) return fail(NTT_ERR_ARG, "primes must be a non-empty array");
+    ntt_plan_s* p = new (std::nothrow) ntt_plan_s();
+    if (!p) return fail(NTT_ERR_NOMEM, "host allocation failed");
+    const ntt_status s = build_plan(p, N, primes, L, opts);
+    if (s != NTT_OK) {
+      delete p;
+      return s;
+    }
+    *out = p;
+    return NTT_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(NTT_ERR_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(NTT_ERR_ARG, "unexpected failure in ntt_plan_create");
+  }
+}
+
+ntt_status ntt_plan_destroy(ntt_plan_t plan) {
+  try {
+    if (!plan) return NTT_OK;
+    DeviceGuard g(plan->device);
+    delete plan;
+    return NTT_OK;
+  } catch (...) {
+    return fail(NTT_ERR_ARG, "unexpected failure in ntt_plan_destroy");
+  }
+}
+
+ntt_status ntt_plan_get_roots(ntt_plan_t plan, uint64_t* psi_out) {
+  if (!plan || !psi_out) return fail(NTT_ERR_ARG, "NULL argument");
+  std::memcpy(psi_out, plan->psis.data(), plan->L * sizeof(uint64_t));
+  return NTT_OK;
+}
+
+ntt_status ntt_plan_get_info(ntt_plan_t plan, uint32_t* N, uint32_t* L, uint32_t* log2_n1, int32_t* twiddle_mode,
+                             int32_t* ot_stages) {
+  if (!plan) return fail(NTT_ERR_ARG, "plan is NULL");
+  if (N) *N = plan->N;
+  if (L) *L = plan->L;
+  if (log2_n1) *log2_n1 = plan->logN1;
+  if (twiddle_mode) *twiddle_mode = plan->twiddle_mode;
+  if (ot_stages) *ot_stages = plan->ot_stages;
+  return NTT_OK;
+}
+
+ntt_status ntt_forward(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, void* stream) {
+  try {
+    ntt_status s = check_data(plan, d_data, n_polys);
+    if (s != NTT_OK) return s;
+    DeviceGuard g(plan->device);
+    if (!g.ok) return fail(NTT_ERR_HIP, "cannot select the plan's device");
+    const hipError_t e = nttk::launch_forward(plan->args(d_data, n_polys, false), plan->active_ot(),
+                                              static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? NTT_OK : hip_fail(e, "ntt_forward launch");
+  } catch (...) {
+    return fail(NTT_ERR_ARG, "unexpected failure in ntt_forward");
+  }
+}
+
+ntt_status ntt_inverse(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, void* stream) {
+  try {
+    ntt_status s = check_data(plan, d_data, n_polys);
+    if (s != NTT_OK) return s;
+    DeviceGuard g(plan->device);
+    if (!g.ok) return fail(NTT_ERR_HIP, "cannot select the plan's device");
+    const hipError_t e = nttk::launch_inverse(plan->args(d_data, n_polys, true), plan->active_ot(),
+                                              static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? NTT_OK : hip_fail(e, "ntt_inverse launch");
+  } catch (...) {
+    return fail(NTT_ERR_ARG, "unexpected failure in ntt_inverse");
+  }
+}
+
+ntt_status ntt_pointwise_mul(ntt_plan_t plan, const uint64_t* d_a, const uint64_t* d_b, uint64_t* d_c,
+                             uint32_t n_polys, void* stream) {
+  try {
+    ntt_status s;
+    if ((s = check_data(plan, d_a, n_polys)) != NTT_OK || (s = check_data(plan, d_b, n_polys)) != NTT_OK ||
+        (s = check_data(plan, d_c, n_polys)) != NTT_OK)
+      return s;
+    DeviceGuard g(plan->device);
+    if (!g.ok) return fail(NTT_ERR_HIP, "cannot select the plan's device");
+    const uint64_t n = (uint64_t)n_polys * plan->L * plan->N;
+    const hipError_t e = nttk::launch_pointwise(d_a, d_b, d_c, plan->d_q, plan->d_mu, plan->d_bits, n, plan->logN,
+                                                plan->L, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? NTT_OK : hip_fail(e, "ntt_pointwise_mul launch");
+  } catch (...) {
+    return fail(NTT_ERR_ARG, "unexpected failure in ntt_pointwise_mul");
+  }
+}
+
+ntt_status ntt_polymul_negacyclic(ntt_plan_t plan, const uint64_t* d_a, const uint64_t* d_b, uint64_t* d_c,
+                                  uint32_t n_polys, void* stream) {
+  try {
+    ntt_status s;
+    if ((s = check_data(plan, d_a, n_polys)) != NTT_OK || (s = check_data(plan, d_b, n_polys)) != NTT_OK ||
+        (s = check_data(plan, d_c, n_polys)) != NTT_OK)
+      return s;
+    if (d_c == d_b) return fail(NTT_ERR_ARG, "d_c must not alias d_b");
+    DeviceGuard g(plan->device);
+    if (!g.ok) return fail(NTT_ERR_HIP, "cannot select the plan's device");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t bytes = (size_t)n_polys * plan->L * plan->N * sizeof(uint64_t);
+
+    std::lock_guard<std::mutex> lk(plan->scratch_mu);
+    hipError_t e;
+    if (plan->scratch_bytes < bytes) {
+      if (plan->scratch_pending && (e = hipEventSynchronize(plan->scratch_ev)) != hipSuccess)
+        return hip_fail(e, "waiting for scratch");
+      if (plan->scratch) (void)hipFree(plan->scratch);
+      plan->scratch = nullptr;
+      plan->scratch_bytes = 0;
+      if ((e = hipMalloc(reinterpret_cast<void**>(&plan->scratch), bytes)) != hipSuccess)
+        return e == hipErrorOutOfMemory ? fail(NTT_ERR_NOMEM, "scratch allocation failed")
+                                        : hip_fail(e, "scratch allocation");
+      plan->scratch_bytes = bytes;
+      plan->scratch_pending = false;
+    }
+    if (plan->scratch_pending && (e = hipStreamWaitEvent(st, plan->scratch_ev, 0)) != hipSuccess)
+      return hip_fail(e, "ordering scratch use");
+    uint64_t* tmp = plan->scratch;
+    if (d_c != d_a && (e = hipMemcpyAsync(d_c, d_a, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+      return hip_fail(e, "copying a");
+    if ((e = hipMemcpyAsync(tmp, d_b, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+      return hip_fail(e, "copying b");
+    const int ot = plan->active_ot();
+    if ((e = nttk::launch_forward(plan->args(d_c, n_polys, false), ot, st)) != hipSuccess ||
+        (e = nttk::launch_forward(plan->args(tmp, n_polys, false), ot, st)) != hipSuccess ||
+        (e = nttk::launch_pointwise(d_c, tmp, d_c, plan->d_q, plan->d_mu, plan->d_bits,
+                                    (uint64_t)n_polys * plan->L * plan->N, plan->logN, plan->L, st)) != hipSuccess ||
+        (e = nttk::launch_inverse(plan->args(d_c, n_polys, true), ot, st)) != hipSuccess)
+      return hip_fail(e, "ntt_polymul_negacyclic launch");
+    if ((e = hipEventRecord(plan->scratch_ev, st)) != hipSuccess) return hip_fail(e, "recording scratch event");
+    plan->scratch_pending = true;
+    return NTT_OK;
+  } catch (...) {
+    return fail(NTT_ERR_ARG, "unexpected failure in ntt_polymul_negacyclic");
+  }
+}
+
+const char* ntt_status_string(ntt_status s) {
+  switch (s) {
+    case NTT_OK: return "NTT_OK";
+    case NTT_ERR_ARG: return "NTT_ERR_ARG";
+    case NTT_ERR_N: return "NTT_ERR_N";
+    case NTT_ERR_PRIME: return "NTT_ERR_PRIME";
+    case NTT_ERR_NOMEM: return "NTT_ERR_NOMEM";
+    case NTT_ERR_HIP: return "NTT_ERR_HIP";
+    case NTT_ERR_UNSUPPORTED: return "NTT_ERR_UNSUPPORTED";
+  }
+  return "NTT_ERR_UNKNOWN";
+}
+
+const char* ntt_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,23 @@
+// Launch interface of the NTT kernels (host side).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nttk {
+
+struct Tw;
+struct PassArgs;
+
+// Whether a (log2 N, log2 N1, OT stages) combination has kernels built in.
+bool shape_supported(uint32_t logN, uint32_t logN1, int ot_stages);
+
+// Forward / inverse transform of every vector described by `a`, enqueued on `st`.
+hipError_t launch_forward(const PassArgs& a, int ot_stages, hipStream_t st);
+hipError_t launch_inverse(const PassArgs& a, int ot_stages, hipStream_t st);
+
+// C = A * B mod q_l element-wise over n_elems elements of a [n_vec][N] batch.
+hipError_t launch_pointwise(const uint64_t* A, const uint64_t* B, uint64_t* C, const uint64_t* qs,
+                            const uint64_t* mus, const uint32_t* bits, uint64_t n_elems, uint32_t logN,
+                            uint32_t L, hipStream_t st);
+
+}  // namespace nttk

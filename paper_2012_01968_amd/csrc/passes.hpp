@@ -1,0 +1,152 @@
+// LDS-staged NTT passes for gfx950.
+//
+// An N-point transform (Algorithm 1: stages m = 1, 2, ..., N/2, twiddle Psi[m + j] for
+// block j) is split as N = N1 * N2 (Section VI-C).  View a limb as an N1 x N2 row-major
+// matrix.  The first log2(N1) stages only pair elements of the same column (stride N2);
+// the remaining log2(N2) stages only pair elements of the same row.  For both passes
+// the twiddle of local stage s and local block j is Psi[(base << s) + j], with
+// base = 1 for a column and base = N1 + row for a row, so one sub-transform routine
+// serves the column pass (Kernel-1 in the paper), the row pass (Kernel-2) and, with
+// N1 = 1, the single-pass kernel used when a whole limb fits in one workgroup.
+//
+// Inside a workgroup each lane holds R = 2^LR values and runs up to LR consecutive
+// stages in registers (the per-thread NTT of Section VI-C); between register steps the
+// values are exchanged through LDS with one barrier.  Register step k of an M-point
+// sub-transform covers the index bits [blo(k), blo(k) + nb(k)) and holds the "window"
+// bits [blo(k), blo(k) + LR); the lane index supplies the remaining bits.  Steps run
+// from the top bit down for the forward transform and in the opposite order for the
+// inverse.
+#pragma once
+#include <type_traits>
+#include "modarith.hpp"
+
+namespace nttk {
+
+struct PassArgs {
+  uint64_t* data;        // batch base, [n_vec][N]
+  const Tw* tw;          // [L][N] twiddles of this direction (Psi or Psi_inv)
+  const Tw* ot_lo;       // [L][B]     psi^{+-k},     k < B       (OT only)
+  const Tw* ot_hi;       // [L][N/B]   psi^{+-B*h},   h < N/B     (OT only)
+  const uint64_t* q;     // [L]
+  const Tw* scale;       // [L][2]: {1/N}, {Psi_inv[1]/N}        (inverse only)
+  uint64_t n_vec;        // vectors in the batch (n_polys * L)
+  uint32_t L;
+  uint32_t logN;
+  uint32_t logN1;        // log2 of the column-pass size (0: single pass)
+  uint32_t ot_log2_base; // log2 B
+};
+
+template <int Begin, int End, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (Begin < End) {
+    f(std::integral_constant<int, Begin>{});
+    static_for<Begin + 1, End>(f);
+  }
+}
+
+template <int Begin, int End, typename F>  // counts down: Begin-1, ..., End
+__device__ __forceinline__ void static_for_down(F&& f) {
+  if constexpr (Begin > End) {
+    f(std::integral_constant<int, Begin - 1>{});
+    static_for_down<Begin - 1, End>(f);
+  }
+}
+
+template <int LOGM, int LR_>
+struct Steps {
+  static constexpr int LR = LR_ < LOGM ? LR_ : LOGM;   // values per lane = 2^LR
+  static constexpr int R = 1 << LR;
+  static constexpr int K = (LOGM + LR - 1) / LR;       // register steps
+  static constexpr int nb(int k) { return k < K - 1 ? LR : LOGM - (K - 1) * LR; }
+  static constexpr int blo(int k) { return k < K - 1 ? LOGM - (k + 1) * LR : 0; }
+  // element index held by lane t in register u during step k
+  template <int k>
+  __device__ static __forceinline__ uint32_t idx(uint32_t t, uint32_t u) {
+    constexpr int lo = blo(k);
+    return ((t >> lo) << (lo + LR)) | (u << lo) | (t & ((1u << lo) - 1u));
+  }
+};
+
+// On-the-fly twiddling (Section VII): Psi[ix] = psi^{e}, e = brv_logN(ix), is split into
+// base-B digits e = e_lo + B * e_hi and applied as two Shoup products with the stored
+// factors psi^{e_lo} and psi^{B * e_hi}.
+struct OtTables {
+  const Tw* lo;
+  const Tw* hi;
+  uint32_t logN;
+  uint32_t b;
+  __device__ __forceinline__ void get(uint32_t ix, Tw& a, Tw& c) const {
+    const uint32_t e = __brev(ix) >> (32 - logN);
+    a = lo[e & ((1u << b) - 1u)];
+    c = hi[e >> b];
+  }
+};
+
+// Forward (Cooley-Tukey) register step K_STEP on the R values of one lane.
+// TabFn(ix) returns the table twiddle Psi[ix]; the last OTS stages of this
+// sub-transform take their twiddles from `ot` instead.
+template <int LOGM, int LR, int K_STEP, int OTS, int NR, typename TabFn>
+__device__ __forceinline__ void ct_step(uint64_t (&x)[NR], uint32_t t, uint32_t base,
+                                        TabFn&& tab, const OtTables& ot, uint64_t q, uint64_t q2) {
+  using S = Steps<LOGM, LR>;
+  static_assert(NR == S::R, "register array size");
+  constexpr int lo = S::blo(K_STEP);
+  constexpr int nb = S::nb(K_STEP);
+  static_for_down<lo + nb, lo>([&](auto bit_c) {
+    constexpr int bit = decltype(bit_c)::value;
+    constexpr int s = LOGM - 1 - bit;
+    constexpr int i = bit - lo;
+#pragma unroll
+    for (int u = 0; u < S::R; ++u) {
+      if (u & (1 << i)) continue;
+      const uint32_t r = S::template idx<K_STEP>(t, (uint32_t)u);
+      const uint32_t ix = (base << s) + (r >> (bit + 1));
+      if constexpr (OTS > 0 && s >= LOGM - OTS) {
+        Tw a, c;
+        ot.get(ix, a, c);
+        ct_bfly_ot(x[u], x[u | (1 << i)], a, c, q, q2);
+      } else {
+        const Tw w = tab(ix);
+        ct_bfly(x[u], x[u | (1 << i)], w.w, w.wb, q, q2);
+      }
+    }
+  });
+}
+
+// Inverse (Gentleman-Sande) register step K_STEP: stages from the low bit up.
+// SCALE0: this sub-transform holds stage 0 of the whole transform, whose butterfly
+// also applies the 1/N scale (sc0 = 1/N, sc1 = Psi_inv[1]/N).
+template <int LOGM, int LR, int K_STEP, int OTS, bool SCALE0, int NR, typename TabFn>
+__device__ __forceinline__ void gs_step(uint64_t (&x)[NR], uint32_t t, uint32_t base,
+                                        TabFn&& tab, const OtTables& ot, uint64_t q, uint64_t q2,
+                                        const Tw& sc0, const Tw& sc1) {
+  using S = Steps<LOGM, LR>;
+  static_assert(NR == S::R, "register array size");
+  constexpr int lo = S::blo(K_STEP);
+  constexpr int nb = S::nb(K_STEP);
+  static_for<lo, lo + nb>([&](auto bit_c) {
+    constexpr int bit = decltype(bit_c)::value;
+    constexpr int s = LOGM - 1 - bit;
+    constexpr int i = bit - lo;
+#pragma unroll
+    for (int u = 0; u < S::R; ++u) {
+      if (u & (1 << i)) continue;
+      if constexpr (SCALE0 && s == 0) {
+        gs_bfly_scaled(x[u], x[u | (1 << i)], sc1, sc0, q, q2);
+      } else {
+        const uint32_t r = S::template idx<K_STEP>(t, (uint32_t)u);
+        const uint32_t ix = (base << s) + (r >> (bit + 1));
+        if constexpr (OTS > 0 && s >= LOGM - OTS) {
+          Tw a, c;
+          ot.get(ix, a, c);
+          gs_bfly_ot(x[u], x[u | (1 << i)], a, c, q, q2);
+        } else {
+          const Tw w = tab(ix);
+          gs_bfly(x[u], x[u | (1 << i)], w.w, w.wb, q, q2);
+        }
+      }
+    }
+  });
+}
+
+}  // namespace nttk

@@ -1,0 +1,87 @@
+"""Host-side checks of the C ABI that need no GPU: every declared symbol is exported,
+status strings, and argument validation that fails before any device work."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ntt_mi355x.h")
+LIB = os.path.join(ROOT, "paper_2012_01968_amd", "libntt_mi355x.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ntt_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("library not built: run python -m paper_2012_01968_amd.build")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("ntt_plan_create", "ntt_plan_destroy", "ntt_plan_get_roots", "ntt_forward", "ntt_inverse",
+                     "ntt_pointwise_mul", "ntt_polymul_negacyclic", "ntt_status_string"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    for name in declared_functions():
+        assert name in exported, name
+        assert getattr(lib, name) is not None
+
+
+def test_status_strings(lib):
+    lib.ntt_status_string.restype = ctypes.c_char_p
+    want = {0: b"NTT_OK", -1: b"NTT_ERR_ARG", -2: b"NTT_ERR_N", -3: b"NTT_ERR_PRIME", -4: b"NTT_ERR_NOMEM",
+            -5: b"NTT_ERR_HIP", -6: b"NTT_ERR_UNSUPPORTED"}
+    for code, name in want.items():
+        assert lib.ntt_status_string(code) == name
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("twiddle_mode", ctypes.c_int32), ("ot_stages", ctypes.c_int32),
+                ("ot_log2_base", ctypes.c_int32), ("log2_n1", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+def _create(lib, N, primes, opts=None):
+    lib.ntt_plan_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32,
+                                    ctypes.POINTER(ctypes.c_uint64), ctypes.c_uint32, ctypes.POINTER(_Opts)]
+    lib.ntt_plan_create.restype = ctypes.c_int
+    h = ctypes.c_void_p(1234)
+    arr = (ctypes.c_uint64 * max(1, len(primes)))(*primes)
+    rc = lib.ntt_plan_create(ctypes.byref(h), N, arr, len(primes), ctypes.byref(opts) if opts else None)
+    return rc, h.value
+
+
+def test_argument_errors_are_synchronous(lib):
+    import synth
+    q = synth.gen_primes(5, 1 << 17, 60, 1)[0]   # 60-bit prime, 1 mod 2^18
+    assert _create(lib, 0, [q]) == (-2, None)
+    assert _create(lib, 3, [q]) == (-2, None)
+    assert _create(lib, 1 << 18, [q]) == (-2, None)
+    assert _create(lib, 1 << 10, [q + 2]) == (-3, None)           # not 1 mod 2N
+    assert _create(lib, 1 << 10, [q, q]) == (-3, None)             # repeated
+    assert _create(lib, 1 << 10, [(1 << 62) + 1]) == (-3, None)    # too large
+    assert _create(lib, 1 << 10, [1 + (1 << 11) * 3 * 5]) == (-3, None)  # 30721 = 31*991: composite, 1 mod 2N
+    assert _create(lib, 1 << 10, []) == (-1, None)
+    o = _Opts()
+    o.reserved[0] = 1
+    assert _create(lib, 1 << 10, [q], o) == (-1, None)
+    o = _Opts(2, 2, 10, 0)
+    assert _create(lib, 1 << 10, [q], o) == (-6, None)             # OT base must be below N
+    o = _Opts(0, 0, 0, 11)
+    assert _create(lib, 1 << 16, [q], o) == (-6, None)             # no column pass of 2^11
+    lib.ntt_forward.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p]
+    lib.ntt_forward.restype = ctypes.c_int
+    assert lib.ntt_forward(None, None, 1, None) == -1

@@ -1,0 +1,241 @@
+"""Bit-exact parity of the HIP path against the CPU oracle, through the C ABI.
+
+Every comparison is exact (tolerance 0): the arithmetic is integer, so exactly one
+correct output exists for each (prime, root convention, output order).  Inputs come
+from ``synth``; expected values come only from ``oracle``.
+"""
+import os
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+ntt = pytest.importorskip("paper_2012_01968_amd")
+
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to("cuda")
+
+
+def host(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def make(N, L, P, bits, seed, n_max=None):
+    primes = synth.gen_primes(seed, n_max or N, bits, L)
+    data = synth.residue_batch(seed, primes, N, P)
+    return primes, oracle.roots(primes, N), data
+
+
+def run_fwd(plan, data):
+    d = dev(data)
+    ntt.ntt_forward(plan, d)
+    torch.cuda.synchronize()
+    return host(d)
+
+
+def run_inv(plan, data):
+    d = dev(data)
+    ntt.ntt_inverse(plan, d)
+    torch.cuda.synchronize()
+    return host(d)
+
+
+def check_fwd_inv(N, L, P, bits, seed, **opts):
+    primes, psis, data = make(N, L, P, bits, seed)
+    plan = ntt.ntt_plan_create(N, primes, **opts)
+    try:
+        assert ntt.ntt_plan_get_roots(plan) == psis
+        want = oracle.forward(data, primes, psis, THREADS)
+        got = run_fwd(plan, data)
+        assert np.array_equal(got, want), f"forward mismatch N={N} opts={opts}"
+        back = run_inv(plan, want)
+        assert np.array_equal(back, data), f"inverse(forward) mismatch N={N} opts={opts}"
+        # inverse of arbitrary NTT-domain vectors against the oracle's inverse
+        want_i = oracle.inverse(data, primes, psis, THREADS)
+        assert np.array_equal(run_inv(plan, data), want_i), f"inverse mismatch N={N} opts={opts}"
+    finally:
+        plan.destroy()
+
+
+# ------------------------------------------------------------------ every size
+
+@pytest.mark.parametrize("logN", list(range(1, 18)))
+def test_every_size_table(logN):
+    N = 1 << logN
+    L, P = (3, 2) if logN >= 12 else (5, 3)   # small sizes: ragged vector counts per workgroup
+    check_fwd_inv(N, L, P, 60, 100 + logN)
+
+
+@pytest.mark.parametrize("logN", [11, 12, 13, 14, 15, 16, 17])
+@pytest.mark.parametrize("ots", [1, 2])
+def test_every_size_ot(logN, ots):
+    check_fwd_inv(1 << logN, 3, 2, 60, 200 + logN, twiddle_mode=ntt.TWIDDLE_OT, ot_stages=ots)
+
+
+@pytest.mark.parametrize("logN,base", [(4, 2), (6, 3), (8, 4), (10, 5)])
+def test_ot_small_bases(logN, base):
+    check_fwd_inv(1 << logN, 4, 3, 60, 300 + logN, twiddle_mode=ntt.TWIDDLE_OT, ot_stages=2, ot_log2_base=base)
+
+
+@pytest.mark.parametrize("logN,n1", [(13, -1), (13, 4), (13, 9), (14, 4), (14, 10), (15, 5), (16, 4), (16, 6),
+                                     (16, 7), (16, 9), (16, 10), (17, 4), (17, 7), (17, 9), (17, 10)])
+def test_pass_splits(logN, n1):
+    check_fwd_inv(1 << logN, 2, 2, 60, 400 + logN, log2_n1=n1)
+    check_fwd_inv(1 << logN, 2, 1, 60, 450 + logN, log2_n1=n1, twiddle_mode=ntt.TWIDDLE_OT, ot_stages=2)
+
+
+# ------------------------------------------------------------------ edge values
+
+@pytest.mark.parametrize("bits", [31, 54, 62])
+def test_prime_widths(bits):
+    # 62-bit primes stretch the lazy ranges to their limit (4q < 2^64)
+    check_fwd_inv(1 << 16, 3, 2, bits, 500 + bits)
+    check_fwd_inv(1 << 12, 3, 2, bits, 520 + bits, twiddle_mode=ntt.TWIDDLE_OT, ot_stages=2)
+
+
+@pytest.mark.parametrize("logN", [12, 16])
+def test_extreme_inputs(logN):
+    N = 1 << logN
+    primes = synth.gen_primes(600, N, 62, 2)
+    psis = oracle.roots(primes, N)
+    plan = ntt.ntt_plan_create(N, primes)
+    try:
+        zeros = np.zeros((1, 2, N), dtype=np.uint64)
+        assert not run_fwd(plan, zeros).any()
+        top = np.empty((1, 2, N), dtype=np.uint64)
+        for l, q in enumerate(primes):
+            top[0, l] = q - 1
+        assert np.array_equal(run_fwd(plan, top), oracle.forward(top, primes, psis))
+        assert np.array_equal(run_inv(plan, top), oracle.inverse(top, primes, psis))
+        e0 = zeros.copy()
+        e0[0, :, 0] = 1
+        assert np.array_equal(run_fwd(plan, e0), np.ones_like(e0))
+        assert np.array_equal(run_inv(plan, np.ones_like(e0)), e0)
+    finally:
+        plan.destroy()
+
+
+# ------------------------------------------------------------------ products
+
+@pytest.mark.parametrize("logN", [3, 10, 12, 16])
+def test_pointwise_and_polymul(logN):
+    N = 1 << logN
+    L = 3
+    primes, psis, a = make(N, L, 2, 60, 700 + logN)
+    b = synth.residue_batch(701 + logN, primes, N, 2)
+    b[0, :, :4] = np.array(primes, dtype=np.uint64)[:, None] - np.uint64(1)   # q - 1 edge values
+    plan = ntt.ntt_plan_create(N, primes)
+    try:
+        da, db, dc = dev(a), dev(b), dev(np.zeros_like(a))
+        ntt.ntt_pointwise_mul(plan, da, db, dc)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(dc), oracle.pointwise(a, b, primes))
+        ntt.ntt_polymul_negacyclic(plan, da, db, dc)
+        torch.cuda.synchronize()
+        want = oracle.polymul(a, b, primes, psis, THREADS)
+        assert np.array_equal(host(dc), want)
+        assert np.array_equal(host(da), a) and np.array_equal(host(db), b)   # inputs untouched
+        if N <= 1 << 10:
+            for l, q in enumerate(primes):
+                assert host(dc)[1, l].tolist() == oracle.schoolbook(a[1, l], b[1, l], q).tolist()
+        ntt.ntt_polymul_negacyclic(plan, da, db, da)   # in place on a
+        torch.cuda.synchronize()
+        assert np.array_equal(host(da), want)
+    finally:
+        plan.destroy()
+
+
+# ------------------------------------------------------------------ benchmark workloads at full size
+
+def test_config1_plain_small():
+    """N=2^12, L=4 primes of 54 bits (seed 1): forward+inverse of one polynomial and the
+    negacyclic product of two."""
+    N, L = 1 << 12, 4
+    primes, psis, data = make(N, L, 2, 54, 1)
+    plan = ntt.ntt_plan_create(N, primes)
+    try:
+        f = run_fwd(plan, data[:1])
+        assert np.array_equal(f, oracle.forward(data[:1], primes, psis))
+        assert np.array_equal(run_inv(plan, f), data[:1])
+        da, db, dc = dev(data[:1]), dev(data[1:]), dev(np.zeros_like(data[:1]))
+        ntt.ntt_polymul_negacyclic(plan, da, db, dc)
+        torch.cuda.synchronize()
+        got = host(dc)
+        for l, q in enumerate(primes):
+            assert got[0, l].tolist() == oracle.schoolbook(data[0, l], data[1, l], q).tolist()
+    finally:
+        plan.destroy()
+
+
+@pytest.mark.parametrize("mode", ["table", "ot"])
+def test_config2_full(mode):
+    """N=2^16, L=45 primes in [2^59, 2^60) (seed 2), one ciphertext (2 polys): forward then inverse."""
+    N, L, P = 1 << 16, 45, 2
+    primes, psis, data = make(N, L, P, 60, 2)
+    opts = {} if mode == "table" else dict(twiddle_mode=ntt.TWIDDLE_OT, ot_stages=2)
+    plan = ntt.ntt_plan_create(N, primes, **opts)
+    try:
+        d = dev(data)
+        ntt.ntt_forward(plan, d)
+        torch.cuda.synchronize()
+        f = host(d)
+        assert np.array_equal(f, oracle.forward(data, primes, psis, THREADS))
+        rnd = random.Random(2)
+        for _ in range(8):   # slots checked against the definition itself (Horner), not Algorithm 1
+            p, l, i = rnd.randrange(P), rnd.randrange(L), rnd.randrange(N)
+            assert int(f[p, l, i]) == oracle.forward_at(data[p, l], primes[l], psis[l], i)
+        ntt.ntt_inverse(plan, d)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(d), data)
+    finally:
+        plan.destroy()
+
+
+def test_config3_full_polymul():
+    """N=2^17, L=60 (seed 3), 4 polys: forward x4, products p0*p2 and p1*p3, inverse x2, OT on."""
+    N, L, P = 1 << 17, 60, 4
+    primes, psis, data = make(N, L, P, 60, 3)
+    plan = ntt.ntt_plan_create(N, primes, twiddle_mode=ntt.TWIDDLE_OT, ot_stages=2)
+    try:
+        d = dev(data)
+        ntt.ntt_forward(plan, d)
+        prod = torch.empty_like(d[:2])
+        ntt.ntt_pointwise_mul(plan, d[:2], d[2:], prod)
+        ntt.ntt_inverse(plan, prod)
+        torch.cuda.synchronize()
+        got = host(prod)
+        f = host(d)
+        rnd = random.Random(3)
+        for _ in range(6):
+            p, l, i = rnd.randrange(P), rnd.randrange(L), rnd.randrange(N)
+            assert int(f[p, l, i]) == oracle.forward_at(data[p, l], primes[l], psis[l], i)
+        want = oracle.polymul(data[:2], data[2:], primes, psis, THREADS)
+        assert np.array_equal(got, want)
+    finally:
+        plan.destroy()
+
+
+def test_plan_reuse_across_streams():
+    N, L = 1 << 14, 4
+    primes, psis, data = make(N, L, 2, 60, 800)
+    plan = ntt.ntt_plan_create(N, primes)
+    try:
+        want = oracle.forward(data, primes, psis)
+        s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+        d1, d2 = dev(data), dev(data)
+        torch.cuda.synchronize()
+        ntt.ntt_forward(plan, d1, stream=s1)
+        ntt.ntt_forward(plan, d2, stream=s2)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(d1), want) and np.array_equal(host(d2), want)
+    finally:
+        plan.destroy()
