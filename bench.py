@@ -1,0 +1,274 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched negacyclic NTT on one MI355X.
+
+Workload (the headline configuration): N = 2^16, L = 45 primes in [2^59, 2^60) drawn
+from seed 2, one ciphertext = 2 polynomials of uniform residues; one step is the
+forward NTT of the whole ciphertext followed by its inverse, i.e. 180 limb-NTTs.
+
+Inputs are resident in HBM before timing starts.  The step rotates through copies of
+the ciphertext totalling more than the 256 MB Infinity Cache, so every step reads its
+input from HBM.  Forward then inverse returns each buffer to its original content, so
+the copies stay valid for the whole run.
+
+Printed (stdout, one JSON line): limb-NTTs/s over the timed steps, the roofline of the
+dominant kernel (algorithmic bytes of one launch / its average duration from HIP events
+on the launch stream), per-step p50/p99, the plain one-call-per-polynomial rate, and the
+CPU oracle timed on this host.  Everything else goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "NTTs/s + % HBM roofline at N=2^16×45 limbs; batched vs plain, p99 latency"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+WORKLOAD = dict(N=1 << 16, L=45, P=2, bits=60, seed=2)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2012_01968_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel: str, src_hash: str):
+    """HBM bytes per launch from the committed counter summary, if it matches this source."""
+    path = os.path.join(ROOT, "profiles", "traffic_counters.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#") or ":" not in line:
+            continue
+        k, v = line.split(":", 1)
+        rec[k.strip()] = v.strip()
+    if rec.get("source_hash") != src_hash:
+        return None
+    key = f"bytes_per_launch[{kernel}]"
+    return float(rec[key]) if key in rec else None
+
+
+def twiddle_bytes(pass_kind: str, N: int, L: int, log2_n1: int, ots: int, b: int = 10) -> int:
+    """Algorithmic twiddle bytes of one launch (16 B per entry: value and Shoup companion)."""
+    N1 = 1 << log2_n1
+    if pass_kind == "col":
+        return 16 * L * N1
+    if log2_n1 == 0:
+        N1 = 1
+    table = N // (1 << ots) - N1
+    ot = ((1 << b) + N // (1 << b)) if ots else 0
+    return 16 * L * (table + ot)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--twiddle", choices=["auto", "table", "ot"], default="auto",
+                    help="auto measures both twiddle modes and reports the faster")
+    ap.add_argument("--log2-n1", type=int, default=0)
+    ap.add_argument("--rotate-gib", type=float, default=1.25, help="total size of the rotating input copies")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        log("bench.py measures one GPU: the transform shards by RNS limb with no exchange, and this "
+            "build runs on a single MI355X, so --gpus above 1 is not supported.")
+        return 2
+
+    import torch
+    import synth
+    import paper_2012_01968_amd as ntt
+
+    N, L, P = WORKLOAD["N"], WORKLOAD["L"], WORKLOAD["P"]
+    primes = synth.gen_primes(WORKLOAD["seed"], N, WORKLOAD["bits"], L)
+    host = synth.residue_batch(WORKLOAD["seed"], primes, N, P)
+    ct_bytes = host.nbytes
+    R = max(2, int(np.ceil(args.rotate_gib * 2**30 / ct_bytes)))
+    dev0 = torch.from_numpy(host.view(np.int64)).to("cuda")
+    bufs = torch.empty((R,) + tuple(dev0.shape), dtype=torch.int64, device="cuda")
+    bufs[:] = dev0
+    torch.cuda.synchronize()
+    log(f"workload N={N} L={L} P={P}: {ct_bytes/1e6:.1f} MB per ciphertext, {R} rotating copies "
+        f"({R*ct_bytes/2**30:.2f} GiB)")
+
+    modes = ["table", "ot"] if args.twiddle == "auto" else [args.twiddle]
+    results = {}
+    for mode in modes:
+        kw = dict(log2_n1=args.log2_n1)
+        if mode == "ot":
+            kw.update(twiddle_mode=ntt.TWIDDLE_OT, ot_stages=2)
+        plan = ntt.ntt_plan_create(N, primes, **kw)
+        info = ntt.ntt_plan_get_info(plan)
+        npass = ntt.ntt_plan_num_passes(plan)
+
+        def step(i):
+            b = bufs[i % R]
+            ntt.ntt_forward(plan, b)
+            ntt.ntt_inverse(plan, b)
+
+        for i in range(args.warmup):
+            step(i)
+        torch.cuda.synchronize()
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        t0 = time.perf_counter()
+        evs[0].record()
+        for i in range(args.steps):
+            step(args.warmup + i)
+            evs[i + 1].record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
+        total_ms = evs[0].elapsed_time(evs[-1])
+        ms = total_ms / args.steps
+
+        # per-kernel durations: the same steps with an event between consecutive kernels
+        names = ([f"fwd_col", "fwd_row"] if npass == 2 else ["fwd_row"]) + \
+                (["inv_row", "inv_col"] if npass == 2 else ["inv_row"])
+        K = args.steps
+        kev = [[torch.cuda.Event(enable_timing=True) for _ in range(2 * npass + 1)] for _ in range(K)]
+        for i in range(K):
+            b = bufs[i % R]
+            e = kev[i]
+            e[0].record()
+            for p in range(npass):
+                ntt.ntt_forward_pass(plan, b, p)
+                e[1 + p].record()
+            for p in range(npass):
+                ntt.ntt_inverse_pass(plan, b, p)
+                e[1 + npass + p].record()
+        torch.cuda.synchronize()
+        kms = {n: float(np.mean([kev[i][j].elapsed_time(kev[i][j + 1]) for i in range(K)]))
+               for j, n in enumerate(names)}
+
+        # plain path: one call per polynomial
+        for i in range(3):
+            for p in range(P):
+                ntt.ntt_forward(plan, bufs[i % R][p])
+                ntt.ntt_inverse(plan, bufs[i % R][p])
+        torch.cuda.synchronize()
+        pe0, pe1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        pe0.record()
+        for i in range(args.steps):
+            b = bufs[i % R]
+            for p in range(P):
+                ntt.ntt_forward(plan, b[p])
+            for p in range(P):
+                ntt.ntt_inverse(plan, b[p])
+        pe1.record()
+        torch.cuda.synchronize()
+        plain_ms = pe0.elapsed_time(pe1) / args.steps
+
+        ok = bool(torch.equal(bufs[0], dev0) and torch.equal(bufs[R - 1], dev0))
+        results[mode] = dict(plan=plan, info=info, npass=npass, ms=ms, per=per, wall=wall, kms=kms,
+                             plain_ms=plain_ms, roundtrip_ok=ok)
+        log(f"[{mode}] {ms*1e3:.1f} us/step  ({180/ms*1e3/1e6:.3f} M NTTs/s)  kernels(us): "
+            + ", ".join(f"{k}={v*1e3:.1f}" for k, v in kms.items())
+            + f"  plain {plain_ms*1e3:.1f} us/step  roundtrip_ok={ok}")
+
+    best = min(results, key=lambda m: results[m]["ms"])
+    r = results[best]
+    info = r["info"]
+    ots = info["ot_stages"] if best == "ot" else 0
+    n_limb_ntts = 2 * P * L
+    value = n_limb_ntts / (r["ms"] * 1e-3)
+
+    # roofline of the dominant kernel
+    dom = max(r["kms"], key=r["kms"].get)
+    kind = "col" if dom.endswith("col") else "row"
+    data_bytes = 16 * P * L * N
+    alg_bytes = data_bytes + twiddle_bytes(kind, N, L, info["log2_n1"], ots)
+    achieved = alg_bytes / (r["kms"][dom] * 1e-3) / 1e9
+    src_hash = kernel_source_hash()
+    traffic = read_traffic(f"{best}:{dom}", src_hash)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                "kernel_us": round(r["kms"][dom] * 1e3, 2), "alg_bytes_per_launch": alg_bytes}
+    step_bytes = 2 * sum(16 * P * L * N + twiddle_bytes(k, N, L, info["log2_n1"], ots)
+                         for k in (["col", "row"] if r["npass"] == 2 else ["row"]))
+    step_frac = step_bytes / (r["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(host, primes, N, r["plan"], bufs, dev0, n_limb_ntts)
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "limb-NTTs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r["ms"], 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "one ciphertext, N=2^16, L=45 primes in [2^59,2^60) (seed 2), 2 polys, "
+                               "forward NTT then inverse NTT (180 limb-NTTs per step)",
+                   "N": N, "L": L, "polys": P, "twiddle": best, "ot_stages": ots,
+                   "log2_n1": info["log2_n1"], "rotating_copies": R},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "step_hbm_frac": round(step_frac, 4),
+        "p50_ms": round(float(np.percentile(r["per"], 50)), 5),
+        "p99_ms": round(float(np.percentile(r["per"], 99)), 5),
+        "plain_value": round(n_limb_ntts / (r["plain_ms"] * 1e-3), 1),
+        "kernel_us": {k: round(v * 1e3, 2) for k, v in r["kms"].items()},
+        "modes_us_per_step": {m: round(results[m]["ms"] * 1e3, 2) for m in results},
+        "roundtrip_ok": r["roundtrip_ok"],
+        "source_hash": src_hash,
+    }
+    for m in results:
+        results[m]["plan"].destroy()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def cpu_baseline(host, primes, N, plan, bufs, dev0, n_limb_ntts):
+    """The CPU oracle (plain C, __int128 %) on this host: forward + inverse of the same
+    ciphertext, repeated until about 3 s of wall time; also checks the GPU forward output
+    of that ciphertext against the oracle's."""
+    import torch
+    import oracle
+    import paper_2012_01968_amd as ntt
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+    psis = oracle.roots(primes, N)
+    reps = 0
+    t0 = time.perf_counter()
+    f = None
+    while True:
+        f = oracle.forward(host, primes, psis, threads)
+        back = oracle.inverse(f, primes, psis, threads)
+        reps += 1
+        if time.perf_counter() - t0 > 3.0:
+            break
+    wall = time.perf_counter() - t0
+    d = dev0.clone()
+    ntt.ntt_forward(plan, d)
+    torch.cuda.synchronize()
+    parity = bool(np.array_equal(d.cpu().numpy().view(np.uint64), f) and np.array_equal(back, host))
+    log(f"cpu oracle: {reps} step(s) in {wall:.2f} s on {threads} threads; GPU forward parity={parity}")
+    return {"value": round(n_limb_ntts * reps / wall, 1), "unit": "limb-NTTs/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{reps} full step(s): forward+inverse of the 2x45x2^16 ciphertext (radix-2, __int128 %)",
+            "gpu_forward_matches": parity}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

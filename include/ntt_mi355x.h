@@ -101,6 +101,22 @@ ntt_status ntt_plan_get_info(ntt_plan_t plan, uint32_t* N, uint32_t* L, uint32_t
  * column pass and row pass (Section VI-C).  Output in bit-reversed order. */
 ntt_status ntt_forward(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, void* stream);
 
+/* One kernel of the forward transform, for callers that schedule or time the passes
+ * themselves (Section VI-C's Kernel-1 / Kernel-2).  pass 0 runs the column pass (the
+ * first log2 N1 stages), pass 1 the row pass (the remaining stages, final reduction,
+ * bit-reversed output).  A single-pass plan (log2_n1 = 0) has only pass 0.  Running
+ * every pass in order equals ntt_forward.  Errors: NTT_ERR_ARG for a pass index at or
+ * above ntt_plan_num_passes. */
+ntt_status ntt_forward_pass(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, uint32_t pass, void* stream);
+
+/* One kernel of the inverse transform: pass 0 runs the row pass (the first
+ * Gentleman-Sande stages), pass 1 the column pass (the last stages with the 1/N scale).
+ * A single-pass plan has only pass 0.  Running every pass in order equals ntt_inverse. */
+ntt_status ntt_inverse_pass(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, uint32_t pass, void* stream);
+
+/* Number of kernels per transform for this plan: 1 (single pass) or 2. */
+uint32_t ntt_plan_num_passes(ntt_plan_t plan);
+
 /* In-place inverse: takes bit-reversed NTT-domain vectors and returns natural-order
  * coefficients, with the Psi^{-1} twist and the 1/N scale merged in (Section III-A). */
 ntt_status ntt_inverse(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, void* stream);

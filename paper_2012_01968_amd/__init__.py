@@ -7,7 +7,7 @@ or as raw integer device addresses.  Streams may be torch streams, raw hipStream
 integers, or None for torch's current stream.
 
 Loading fails loudly (ImportError) when the built library is missing: there is no
-fallback path.  Build it with ``python -m paper_2012_01968_amd.build``.
+fallback path.  Build it with ``python paper_2012_01968_amd/build.py``.
 """
 from __future__ import annotations
 
@@ -16,7 +16,8 @@ import os
 
 __all__ = [
     "NttError", "Plan", "ntt_plan_create", "ntt_plan_destroy", "ntt_plan_get_roots", "ntt_plan_get_info",
-    "ntt_forward", "ntt_inverse", "ntt_pointwise_mul", "ntt_polymul_negacyclic", "ntt_status_string",
+    "ntt_forward", "ntt_inverse", "ntt_forward_pass", "ntt_inverse_pass", "ntt_plan_num_passes",
+    "ntt_pointwise_mul", "ntt_polymul_negacyclic", "ntt_status_string",
     "library_path", "TWIDDLE_AUTO", "TWIDDLE_TABLE", "TWIDDLE_OT",
 ]
 
@@ -31,7 +32,7 @@ def library_path() -> str:
 
 
 if not os.path.exists(_LIB_PATH):
-    raise ImportError(f"{_LIB_PATH} is not built; run `python -m paper_2012_01968_amd.build`")
+    raise ImportError(f"{_LIB_PATH} is not built; run `python paper_2012_01968_amd/build.py`")
 
 _lib = ctypes.CDLL(_LIB_PATH)
 
@@ -52,6 +53,10 @@ _lib.ntt_plan_get_info.argtypes = [_vp, ctypes.POINTER(_u32), ctypes.POINTER(_u3
                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
 _lib.ntt_forward.argtypes = [_vp, _vp, _u32, _vp]
 _lib.ntt_inverse.argtypes = [_vp, _vp, _u32, _vp]
+_lib.ntt_forward_pass.argtypes = [_vp, _vp, _u32, _u32, _vp]
+_lib.ntt_inverse_pass.argtypes = [_vp, _vp, _u32, _u32, _vp]
+_lib.ntt_plan_num_passes.argtypes = [_vp]
+_lib.ntt_plan_num_passes.restype = _u32
 _lib.ntt_pointwise_mul.argtypes = [_vp, _vp, _vp, _vp, _u32, _vp]
 _lib.ntt_polymul_negacyclic.argtypes = [_vp, _vp, _vp, _vp, _u32, _vp]
 _lib.ntt_status_string.argtypes = [ctypes.c_int]
@@ -59,7 +64,7 @@ _lib.ntt_status_string.restype = ctypes.c_char_p
 _lib.ntt_last_error.argtypes = []
 _lib.ntt_last_error.restype = ctypes.c_char_p
 for _f in ("ntt_plan_create", "ntt_plan_destroy", "ntt_plan_get_roots", "ntt_plan_get_info", "ntt_forward",
-           "ntt_inverse", "ntt_pointwise_mul", "ntt_polymul_negacyclic"):
+           "ntt_inverse", "ntt_forward_pass", "ntt_inverse_pass", "ntt_pointwise_mul", "ntt_polymul_negacyclic"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -160,6 +165,20 @@ def ntt_forward(plan: Plan, data, n_polys: int | None = None, stream=None) -> No
 
 def ntt_inverse(plan: Plan, data, n_polys: int | None = None, stream=None) -> None:
     _check(_lib.ntt_inverse(plan.handle, _addr(data), _polys(plan, data, n_polys), _stream(stream)), "ntt_inverse")
+
+
+def ntt_forward_pass(plan: Plan, data, pass_index: int, n_polys: int | None = None, stream=None) -> None:
+    _check(_lib.ntt_forward_pass(plan.handle, _addr(data), _polys(plan, data, n_polys), pass_index, _stream(stream)),
+           "ntt_forward_pass")
+
+
+def ntt_inverse_pass(plan: Plan, data, pass_index: int, n_polys: int | None = None, stream=None) -> None:
+    _check(_lib.ntt_inverse_pass(plan.handle, _addr(data), _polys(plan, data, n_polys), pass_index, _stream(stream)),
+           "ntt_inverse_pass")
+
+
+def ntt_plan_num_passes(plan: Plan) -> int:
+    return int(_lib.ntt_plan_num_passes(plan.handle))
 
 
 def ntt_pointwise_mul(plan: Plan, a, b, c, n_polys: int | None = None, stream=None) -> None:

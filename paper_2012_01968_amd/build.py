@@ -1,7 +1,8 @@
 """Build the HIP library in-tree: paper_2012_01968_amd/libntt_mi355x.so (gfx950).
 
 Each translation unit is compiled by hipcc into _build/ in parallel, then linked into a
-shared library next to this file.  Run ``python -m paper_2012_01968_amd.build``.
+shared library next to this file.  Run ``python paper_2012_01968_amd/build.py`` (as a
+script: importing the package needs the library this builds).
 """
 from __future__ import annotations
 
@@ -15,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build", "ntt")
 LIB = os.path.join(HERE, "libntt_mi355x.so")
-SOURCES = ["kernels.hip", "capi.cpp"]
+SOURCES = ["kernels_fwd_fast.hip", "kernels_inv_fast.hip", "kernels_fwd_wide.hip", "kernels_inv_wide.hip",
+           "kernels.hip", "capi.cpp"]
 ARCH = os.environ.get("NTT_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

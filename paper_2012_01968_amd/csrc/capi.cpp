@@ -67,6 +67,7 @@ struct ntt_plan_s {
   int32_t ot_stages = 0;
   uint32_t ot_log2_base = 10;
   int device = 0;
+  bool fast = false;  // all primes below 2^60 (wider lazy ranges, estimated quotients)
   std::vector<uint64_t> primes, psis;
 
   uint64_t* d_q = nullptr;
@@ -111,6 +112,7 @@ struct ntt_plan_s {
     a.logN = logN;
     a.logN1 = logN1;
     a.ot_log2_base = ot_log2_base;
+    a.fast = fast ? 1u : 0u;
     return a;
   }
   int active_ot() const { return twiddle_mode == NTT_TWIDDLE_OT ? ot_stages : 0; }
@@ -163,6 +165,8 @@ static ntt_status build_plan(ntt_plan_s* p, uint32_t N, const uint64_t* primes, 
     if ((q - 1) % (2ull * N)) return fail(NTT_ERR_PRIME, "prime " + std::to_string(q) + " is not 1 mod 2N");
     if (!nttp::is_prime(q)) return fail(NTT_ERR_PRIME, std::to_string(q) + " is not prime");
   }
+
+  p->fast = *std::max_element(p->primes.begin(), p->primes.end()) < (1ull << 60);
 
   // ---- tables (host), one worker per block of limbs
   const size_t NN = N;
@@ -321,6 +325,34 @@ ntt_status ntt_forward(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, void
   } catch (...) {
     return fail(NTT_ERR_ARG, "unexpected failure in ntt_forward");
   }
+}
+
+uint32_t ntt_plan_num_passes(ntt_plan_t plan) { return plan ? (plan->logN1 ? 2u : 1u) : 0u; }
+
+static ntt_status run_pass(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, uint32_t pass, void* stream,
+                           bool inverse) {
+  try {
+    ntt_status s = check_data(plan, d_data, n_polys);
+    if (s != NTT_OK) return s;
+    if (pass >= ntt_plan_num_passes(plan)) return fail(NTT_ERR_ARG, "pass index out of range");
+    DeviceGuard g(plan->device);
+    if (!g.ok) return fail(NTT_ERR_HIP, "cannot select the plan's device");
+    const PassArgs a = plan->args(d_data, n_polys, inverse);
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const hipError_t e = inverse ? nttk::launch_inverse_pass(a, plan->active_ot(), (int)pass, st)
+                                 : nttk::launch_forward_pass(a, plan->active_ot(), (int)pass, st);
+    return e == hipSuccess ? NTT_OK : hip_fail(e, "pass launch");
+  } catch (...) {
+    return fail(NTT_ERR_ARG, "unexpected failure in a pass launch");
+  }
+}
+
+ntt_status ntt_forward_pass(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, uint32_t pass, void* stream) {
+  return run_pass(plan, d_data, n_polys, pass, stream, false);
+}
+
+ntt_status ntt_inverse_pass(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, uint32_t pass, void* stream) {
+  return run_pass(plan, d_data, n_polys, pass, stream, true);
 }
 
 ntt_status ntt_inverse(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, void* stream) {

@@ -1,247 +1,17 @@
-// NTT kernels for gfx950: the LDS-staged column pass and row pass of Section VI-C in
-// both directions, plus the element-wise product.  See passes.hpp for the split.
+// NTT launch entry points (host) and the element-wise product kernel.
 #include "kernels.hpp"
 #include "passes.hpp"
 
 namespace nttk {
 
-constexpr int kLR = 4;          // 16 values per lane per register step
-constexpr int kColWidth = 16;   // columns per column-pass workgroup: 16 x 8 B = one 128 B line
-
-__device__ __forceinline__ uint32_t lds_pad(uint32_t r) { return r + (r >> 4); }
-
-template <int LOGM>
-struct RowCfg {
-  using S = Steps<LOGM, kLR>;
-  static constexpr int M = 1 << LOGM;
-  static constexpr int T = M / S::R;                    // lanes per row
-  static constexpr int V = T >= 256 ? 1 : 256 / T;      // rows per workgroup
-  static constexpr int NT = V * T;
-  static constexpr int PITCH = M >= 16 ? M + M / 16 : M;
-};
-
-// ----------------------------------------------------------------------------- row pass
-// Rows of length M = N / N1, V rows per workgroup; row g of the batch starts at
-// data + g*M, belongs to vector g / N1 and is row g mod N1 of that vector's matrix.
-
-template <int LOGM, int OTS>
-__global__ __launch_bounds__(RowCfg<LOGM>::NT) void fwd_row_kernel(PassArgs a) {
-  using C = RowCfg<LOGM>;
-  using S = typename C::S;
-  __shared__ uint64_t lds[C::V * C::PITCH];
-  const uint32_t tid = threadIdx.x, v = tid / C::T, t = tid % C::T;
-  const uint64_t rows = a.n_vec << a.logN1;
-  const uint64_t g0 = (uint64_t)blockIdx.x * C::V + v;
-  const bool valid = g0 < rows;
-  const uint64_t g = valid ? g0 : 0;
-  const uint32_t N1 = 1u << a.logN1;
-  const uint32_t limb = (uint32_t)((g >> a.logN1) % a.L);
-  const uint64_t q = a.q[limb], q2 = q << 1;
-  const uint32_t base = N1 + (uint32_t)(g & (N1 - 1));
-  const Tw* tab = a.tw + ((size_t)limb << a.logN);
-  OtTables ot{};
-  if constexpr (OTS > 0) {
-    ot.lo = a.ot_lo + ((size_t)limb << a.ot_log2_base);
-    ot.hi = a.ot_hi + ((size_t)limb << (a.logN - a.ot_log2_base));
-    ot.logN = a.logN;
-    ot.b = a.ot_log2_base;
-  }
-  auto tabfn = [&](uint32_t ix) { return tab[ix]; };
-  uint64_t* rowp = a.data + g * C::M;
-  uint64_t* l = lds + v * C::PITCH;
-
-  uint64_t x[S::R];
-#pragma unroll
-  for (int u = 0; u < S::R; ++u) x[u] = valid ? rowp[S::template idx<0>(t, u)] : 0;
-
-  static_for<0, S::K>([&](auto kc) {
-    constexpr int k = decltype(kc)::value;
-    if constexpr (k > 0) {
-#pragma unroll
-      for (int u = 0; u < S::R; ++u) l[lds_pad(S::template idx<k - 1>(t, u))] = x[u];
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < S::R; ++u) x[u] = l[lds_pad(S::template idx<k>(t, u))];
-    }
-    ct_step<LOGM, kLR, k, OTS>(x, t, base, tabfn, ot, q, q2);
-  });
-
-#pragma unroll
-  for (int u = 0; u < S::R; ++u) x[u] = canon4(x[u], q, q2);
-  if constexpr (S::K > 1) {
-#pragma unroll
-    for (int u = 0; u < S::R; ++u) l[lds_pad(S::template idx<S::K - 1>(t, u))] = x[u];
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < S::R; ++u) x[u] = l[lds_pad(S::template idx<0>(t, u))];
-  }
-  if (valid) {
-#pragma unroll
-    for (int u = 0; u < S::R; ++u) rowp[S::template idx<0>(t, u)] = x[u];
-  }
-}
-
-// SCALE0: single-pass inverse (N1 = 1), so this pass ends with global stage 0 and
-// applies the 1/N scale and the final reduction.
-template <int LOGM, int OTS, bool SCALE0>
-__global__ __launch_bounds__(RowCfg<LOGM>::NT) void inv_row_kernel(PassArgs a) {
-  using C = RowCfg<LOGM>;
-  using S = typename C::S;
-  __shared__ uint64_t lds[C::V * C::PITCH];
-  const uint32_t tid = threadIdx.x, v = tid / C::T, t = tid % C::T;
-  const uint64_t rows = a.n_vec << a.logN1;
-  const uint64_t g0 = (uint64_t)blockIdx.x * C::V + v;
-  const bool valid = g0 < rows;
-  const uint64_t g = valid ? g0 : 0;
-  const uint32_t N1 = 1u << a.logN1;
-  const uint32_t limb = (uint32_t)((g >> a.logN1) % a.L);
-  const uint64_t q = a.q[limb], q2 = q << 1;
-  const uint32_t base = N1 + (uint32_t)(g & (N1 - 1));
-  const Tw* tab = a.tw + ((size_t)limb << a.logN);
-  OtTables ot{};
-  if constexpr (OTS > 0) {
-    ot.lo = a.ot_lo + ((size_t)limb << a.ot_log2_base);
-    ot.hi = a.ot_hi + ((size_t)limb << (a.logN - a.ot_log2_base));
-    ot.logN = a.logN;
-    ot.b = a.ot_log2_base;
-  }
-  Tw sc0{}, sc1{};
-  if constexpr (SCALE0) {
-    sc0 = a.scale[2 * limb];
-    sc1 = a.scale[2 * limb + 1];
-  }
-  auto tabfn = [&](uint32_t ix) { return tab[ix]; };
-  uint64_t* rowp = a.data + g * C::M;
-  uint64_t* l = lds + v * C::PITCH;
-
-  uint64_t x[S::R];
-#pragma unroll
-  for (int u = 0; u < S::R; ++u) x[u] = valid ? rowp[S::template idx<0>(t, u)] : 0;
-  if constexpr (S::K > 1) {
-#pragma unroll
-    for (int u = 0; u < S::R; ++u) l[lds_pad(S::template idx<0>(t, u))] = x[u];
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < S::R; ++u) x[u] = l[lds_pad(S::template idx<S::K - 1>(t, u))];
-  }
-
-  static_for_down<S::K, 0>([&](auto kc) {
-    constexpr int k = decltype(kc)::value;
-    if constexpr (k < S::K - 1) {
-#pragma unroll
-      for (int u = 0; u < S::R; ++u) l[lds_pad(S::template idx<k + 1>(t, u))] = x[u];
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < S::R; ++u) x[u] = l[lds_pad(S::template idx<k>(t, u))];
-    }
-    gs_step<LOGM, kLR, k, OTS, SCALE0>(x, t, base, tabfn, ot, q, q2, sc0, sc1);
-  });
-
-  if constexpr (SCALE0) {
-#pragma unroll
-    for (int u = 0; u < S::R; ++u) x[u] = canon2(x[u], q);
-  }
-  if (valid) {
-#pragma unroll
-    for (int u = 0; u < S::R; ++u) rowp[S::template idx<0>(t, u)] = x[u];
-  }
-}
-
-// -------------------------------------------------------------------------- column pass
-// kColWidth adjacent columns of one vector per workgroup (the coalesced Kernel-1 of
-// Section VI-C: lanes of a wave cover adjacent columns, so every row segment is one
-// full 128-byte line).  The first N1 twiddles are staged in LDS before use.
-
-template <int LOGM>
-struct ColCfg {
-  using S = Steps<LOGM, kLR>;
-  static constexpr int M = 1 << LOGM;
-  static constexpr int W = kColWidth;
-  static constexpr int T = M / S::R;      // lanes per column
-  static constexpr int NT = W * T;
-  static constexpr int PITCH = W;         // LDS elements per matrix row
-};
-
-template <int LOGM>
-__global__ __launch_bounds__(ColCfg<LOGM>::NT) void fwd_col_kernel(PassArgs a) {
-  using C = ColCfg<LOGM>;
-  using S = typename C::S;
-  __shared__ uint64_t lds[C::M * C::PITCH];
-  __shared__ Tw twl[C::M];
-  const uint32_t tid = threadIdx.x, c = tid % C::W, t = tid / C::W;
-  const uint32_t logN2 = a.logN - LOGM;
-  const uint32_t groups = (1u << logN2) / C::W;
-  const uint64_t vec = blockIdx.x / groups;
-  const uint32_t cg = blockIdx.x % groups;
-  const uint32_t limb = (uint32_t)(vec % a.L);
-  const uint64_t q = a.q[limb], q2 = q << 1;
-  const Tw* tab = a.tw + ((size_t)limb << a.logN);
-  for (uint32_t i = tid; i < (uint32_t)C::M; i += C::NT) twl[i] = tab[i];
-  uint64_t* colp = a.data + (vec << a.logN) + cg * C::W + c;
-
-  uint64_t x[S::R];
-#pragma unroll
-  for (int u = 0; u < S::R; ++u) x[u] = colp[(size_t)S::template idx<0>(t, u) << logN2];
-  __syncthreads();
-  auto tabfn = [&](uint32_t ix) { return twl[ix]; };
-  OtTables ot{};
-
-  static_for<0, S::K>([&](auto kc) {
-    constexpr int k = decltype(kc)::value;
-    if constexpr (k > 0) {
-#pragma unroll
-      for (int u = 0; u < S::R; ++u) lds[S::template idx<k - 1>(t, u) * C::PITCH + c] = x[u];
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < S::R; ++u) x[u] = lds[S::template idx<k>(t, u) * C::PITCH + c];
-    }
-    ct_step<LOGM, kLR, k, 0>(x, t, 1u, tabfn, ot, q, q2);
-  });
-
-#pragma unroll
-  for (int u = 0; u < S::R; ++u) colp[(size_t)S::template idx<S::K - 1>(t, u) << logN2] = x[u];
-}
-
-template <int LOGM>
-__global__ __launch_bounds__(ColCfg<LOGM>::NT) void inv_col_kernel(PassArgs a) {
-  using C = ColCfg<LOGM>;
-  using S = typename C::S;
-  __shared__ uint64_t lds[C::M * C::PITCH];
-  __shared__ Tw twl[C::M];
-  const uint32_t tid = threadIdx.x, c = tid % C::W, t = tid / C::W;
-  const uint32_t logN2 = a.logN - LOGM;
-  const uint32_t groups = (1u << logN2) / C::W;
-  const uint64_t vec = blockIdx.x / groups;
-  const uint32_t cg = blockIdx.x % groups;
-  const uint32_t limb = (uint32_t)(vec % a.L);
-  const uint64_t q = a.q[limb], q2 = q << 1;
-  const Tw* tab = a.tw + ((size_t)limb << a.logN);
-  for (uint32_t i = tid; i < (uint32_t)C::M; i += C::NT) twl[i] = tab[i];
-  const Tw sc0 = a.scale[2 * limb], sc1 = a.scale[2 * limb + 1];
-  uint64_t* colp = a.data + (vec << a.logN) + cg * C::W + c;
-
-  uint64_t x[S::R];
-#pragma unroll
-  for (int u = 0; u < S::R; ++u) x[u] = colp[(size_t)S::template idx<S::K - 1>(t, u) << logN2];
-  __syncthreads();
-  auto tabfn = [&](uint32_t ix) { return twl[ix]; };
-  OtTables ot{};
-
-  static_for_down<S::K, 0>([&](auto kc) {
-    constexpr int k = decltype(kc)::value;
-    if constexpr (k < S::K - 1) {
-#pragma unroll
-      for (int u = 0; u < S::R; ++u) lds[S::template idx<k + 1>(t, u) * C::PITCH + c] = x[u];
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < S::R; ++u) x[u] = lds[S::template idx<k>(t, u) * C::PITCH + c];
-    }
-    gs_step<LOGM, kLR, k, 0, true>(x, t, 1u, tabfn, ot, q, q2, sc0, sc1);
-  });
-
-#pragma unroll
-  for (int u = 0; u < S::R; ++u) colp[(size_t)S::template idx<0>(t, u) << logN2] = canon2(x[u], q);
-}
+template <bool FAST>
+hipError_t forward_pass(const PassArgs& a, int ots, int pass, hipStream_t st);
+template <bool FAST>
+hipError_t inverse_pass(const PassArgs& a, int ots, int pass, hipStream_t st);
+extern template hipError_t forward_pass<true>(const PassArgs&, int, int, hipStream_t);
+extern template hipError_t forward_pass<false>(const PassArgs&, int, int, hipStream_t);
+extern template hipError_t inverse_pass<true>(const PassArgs&, int, int, hipStream_t);
+extern template hipError_t inverse_pass<false>(const PassArgs&, int, int, hipStream_t);
 
 // ------------------------------------------------------------------------ element-wise
 // c = a * b mod q_l over a [n_vec][N] batch, two elements per lane per iteration.
@@ -265,101 +35,6 @@ __global__ __launch_bounds__(256) void pointwise_kernel(const uint64_t* __restri
   }
 }
 
-// ------------------------------------------------------------------------------ launchers
-
-template <int LOGM, int OTS>
-static hipError_t go_fwd_row(const PassArgs& a, hipStream_t st) {
-  using C = RowCfg<LOGM>;
-  const uint64_t rows = a.n_vec << a.logN1;
-  const uint64_t blocks = (rows + C::V - 1) / C::V;
-  hipLaunchKernelGGL((fwd_row_kernel<LOGM, OTS>), dim3((uint32_t)blocks), dim3(C::NT), 0, st, a);
-  return hipGetLastError();
-}
-
-template <int LOGM, int OTS, bool SCALE0>
-static hipError_t go_inv_row(const PassArgs& a, hipStream_t st) {
-  using C = RowCfg<LOGM>;
-  const uint64_t rows = a.n_vec << a.logN1;
-  const uint64_t blocks = (rows + C::V - 1) / C::V;
-  hipLaunchKernelGGL((inv_row_kernel<LOGM, OTS, SCALE0>), dim3((uint32_t)blocks), dim3(C::NT), 0, st, a);
-  return hipGetLastError();
-}
-
-template <int LOGM>
-static hipError_t go_fwd_col(const PassArgs& a, hipStream_t st) {
-  using C = ColCfg<LOGM>;
-  const uint64_t blocks = a.n_vec * ((1u << (a.logN - LOGM)) / C::W);
-  hipLaunchKernelGGL((fwd_col_kernel<LOGM>), dim3((uint32_t)blocks), dim3(C::NT), 0, st, a);
-  return hipGetLastError();
-}
-
-template <int LOGM>
-static hipError_t go_inv_col(const PassArgs& a, hipStream_t st) {
-  using C = ColCfg<LOGM>;
-  const uint64_t blocks = a.n_vec * ((1u << (a.logN - LOGM)) / C::W);
-  hipLaunchKernelGGL((inv_col_kernel<LOGM>), dim3((uint32_t)blocks), dim3(C::NT), 0, st, a);
-  return hipGetLastError();
-}
-
-#define NTTK_ROW_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13)
-#define NTTK_COL_CASES(X) X(4) X(5) X(6) X(7) X(8) X(9) X(10)
-
-static hipError_t fwd_row(const PassArgs& a, int logm, int ots, hipStream_t st) {
-  switch (logm) {
-#define X(LM)                                                   \
-  case LM:                                                      \
-    if (ots == 0) return go_fwd_row<LM, 0>(a, st);              \
-    if (ots == 1) return go_fwd_row<LM, 1>(a, st);              \
-    if (ots == 2) return go_fwd_row<LM, 2>(a, st);              \
-    return hipErrorInvalidValue;
-    NTTK_ROW_CASES(X)
-#undef X
-  }
-  return hipErrorInvalidValue;
-}
-
-static hipError_t inv_row(const PassArgs& a, int logm, int ots, bool scale0, hipStream_t st) {
-  switch (logm) {
-#define X(LM)                                                                      \
-  case LM:                                                                         \
-    if (scale0) {                                                                  \
-      if (ots == 0) return go_inv_row<LM, 0, true>(a, st);                         \
-      if constexpr (LM >= 2) if (ots == 1) return go_inv_row<LM, 1, true>(a, st);  \
-      if constexpr (LM >= 3) if (ots == 2) return go_inv_row<LM, 2, true>(a, st);  \
-    } else {                                                                       \
-      if (ots == 0) return go_inv_row<LM, 0, false>(a, st);                        \
-      if constexpr (LM >= 1) if (ots == 1) return go_inv_row<LM, 1, false>(a, st); \
-      if constexpr (LM >= 2) if (ots == 2) return go_inv_row<LM, 2, false>(a, st); \
-    }                                                                              \
-    return hipErrorInvalidValue;
-    NTTK_ROW_CASES(X)
-#undef X
-  }
-  return hipErrorInvalidValue;
-}
-
-static hipError_t fwd_col(const PassArgs& a, int logm, hipStream_t st) {
-  switch (logm) {
-#define X(LM) \
-  case LM:    \
-    return go_fwd_col<LM>(a, st);
-    NTTK_COL_CASES(X)
-#undef X
-  }
-  return hipErrorInvalidValue;
-}
-
-static hipError_t inv_col(const PassArgs& a, int logm, hipStream_t st) {
-  switch (logm) {
-#define X(LM) \
-  case LM:    \
-    return go_inv_col<LM>(a, st);
-    NTTK_COL_CASES(X)
-#undef X
-  }
-  return hipErrorInvalidValue;
-}
-
 bool shape_supported(uint32_t logN, uint32_t logN1, int ots) {
   if (logN < 1 || logN > 17) return false;
   if (logN1 == 0) {
@@ -372,20 +47,32 @@ bool shape_supported(uint32_t logN, uint32_t logN1, int ots) {
   return ots >= 0 && ots <= 2 && (int)logN2 > ots;
 }
 
-hipError_t launch_forward(const PassArgs& a, int ots, hipStream_t st) {
+hipError_t launch_forward_pass(const PassArgs& a, int ots, int pass, hipStream_t st) {
   if (!shape_supported(a.logN, a.logN1, ots)) return hipErrorInvalidValue;
-  if (a.logN1 == 0) return fwd_row(a, (int)a.logN, ots, st);
-  hipError_t e = fwd_col(a, (int)a.logN1, st);
-  if (e != hipSuccess) return e;
-  return fwd_row(a, (int)(a.logN - a.logN1), ots, st);
+  return a.fast ? forward_pass<true>(a, ots, pass, st) : forward_pass<false>(a, ots, pass, st);
+}
+
+hipError_t launch_inverse_pass(const PassArgs& a, int ots, int pass, hipStream_t st) {
+  if (!shape_supported(a.logN, a.logN1, ots)) return hipErrorInvalidValue;
+  return a.fast ? inverse_pass<true>(a, ots, pass, st) : inverse_pass<false>(a, ots, pass, st);
+}
+
+hipError_t launch_forward(const PassArgs& a, int ots, hipStream_t st) {
+  const int passes = a.logN1 ? 2 : 1;
+  for (int p = 0; p < passes; ++p) {
+    const hipError_t e = launch_forward_pass(a, ots, p, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_inverse(const PassArgs& a, int ots, hipStream_t st) {
-  if (!shape_supported(a.logN, a.logN1, ots)) return hipErrorInvalidValue;
-  if (a.logN1 == 0) return inv_row(a, (int)a.logN, ots, true, st);
-  hipError_t e = inv_row(a, (int)(a.logN - a.logN1), ots, false, st);
-  if (e != hipSuccess) return e;
-  return inv_col(a, (int)a.logN1, st);
+  const int passes = a.logN1 ? 2 : 1;
+  for (int p = 0; p < passes; ++p) {
+    const hipError_t e = launch_inverse_pass(a, ots, p, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_pointwise(const uint64_t* A, const uint64_t* B, uint64_t* Cc, const uint64_t* qs,

@@ -1,0 +1,6 @@
+// Inverse NTT kernels, primes below 2^62 (exact quotients).
+#include "kernels_impl.hpp"
+
+namespace nttk {
+template hipError_t inverse_pass<false>(const PassArgs&, int, int, hipStream_t);
+}  // namespace nttk

@@ -1,4 +1,4 @@
-// Device modular arithmetic for 64-bit NTT-friendly primes q < 2^62 on gfx950.
+// Device modular arithmetic for 64-bit NTT-friendly primes on gfx950.
 //
 // Shoup's modular multiplication (Algorithm 4 of the paper): with the companion
 // wb = floor(w * 2^64 / q) precomputed for a fixed operand w < q, the quotient
@@ -6,12 +6,22 @@
 // b < 2^64, so r = b*w - qh*q lies in [0, 2q) and only the low 64 bits of the two
 // products are needed.  The paper's listing writes the quotient step with a garbled
 // shift and tests `r > p`; the reading here is the high half of the 128-bit product
-// and a lazy result in [0, 2q) (the final canonicalisation happens once, at the end
-// of a transform).
+// and a lazy result (the final reduction to [0, q) happens once, at the end of a
+// transform).  Butterflies keep their values in lazy ranges in the manner of Harvey,
+// whom the paper cites for Algorithm 2's [0, 4p) input bound.
 //
-// Butterflies follow Harvey's lazy form (the paper's Algorithm 2 takes inputs in
-// [0, 4q) and cites Harvey for the bound): the Cooley-Tukey butterfly keeps values in
-// [0, 4q), the Gentleman-Sande butterfly in [0, 2q).  Both need 4q < 2^64.
+// Two arithmetic policies, chosen per plan from the largest prime:
+//
+//  Arith<false>  any q < 2^62.  Exact quotient; Cooley-Tukey values in [0, 4q),
+//                Gentleman-Sande values in [0, 2q) (Harvey's bounds).
+//  Arith<true>   q < 2^60.  The quotient is estimated from the three high partial
+//                products only, b1*wb1 + hi(b0*wb1) + hi(b1*wb0): the dropped terms sum
+//                to less than 3 * 2^64, so the estimate undershoots the exact one by at
+//                most 2 and r lies in [0, 4q).  The low half is formed as
+//                b*w + qh*(2^64 - q) mod 2^64 with the four cross products folded into
+//                the high word.  Cooley-Tukey values live in [0, 8q), Gentleman-Sande
+//                values in [0, 4q); 8q < 2^63 lets the conditional subtraction test the
+//                sign of x - m instead of comparing.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -22,63 +32,127 @@ struct Tw {  // a twiddle and its Shoup companion, stored as one 16-byte entry
   uint64_t w, wb;
 };
 
-__device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
+struct Mod {  // per-prime constants
+  uint64_t q, q2, q4, nq, nq2, nq4;  // q, 2q, 4q, and their negatives mod 2^64
+  __device__ __forceinline__ explicit Mod(uint64_t p)
+      : q(p), q2(p << 1), q4(p << 2), nq(0 - p), nq2(0 - (p << 1)), nq4(0 - (p << 2)) {}
+  Mod() = default;
+};
 
-// b * w mod q in [0, 2q), any b < 2^64.
-__device__ __forceinline__ uint64_t shoup(uint64_t b, uint64_t w, uint64_t wb, uint64_t q) {
-  const uint64_t qh = mulhi64(b, wb);
-  return b * w - qh * q;
-}
+__device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
 
 __device__ __forceinline__ uint64_t csub(uint64_t x, uint64_t m) { return x >= m ? x - m : x; }
 
-// Cooley-Tukey butterfly: X, Y in [0, 4q) -> X + WY, X - WY, both in [0, 4q).
-__device__ __forceinline__ void ct_bfly(uint64_t& X, uint64_t& Y, uint64_t w, uint64_t wb, uint64_t q,
-                                        uint64_t q2) {
-  const uint64_t x = csub(X, q2);
-  const uint64_t t = shoup(Y, w, wb, q);
-  X = x + t;
-  Y = x - t + q2;
+// x - m when x >= m, else x; needs x < 2^63 and m < 2^63 (negm = 2^64 - m).
+__device__ __forceinline__ uint64_t csub_sign(uint64_t x, uint64_t negm) {
+  const uint64_t d = x + negm;
+  return (int64_t)d < 0 ? x : d;
 }
 
-// Same, with the twiddle applied as two Shoup products (on-the-fly twiddling:
-// w = w1 * w2 mod q is never formed, Section VII).
-__device__ __forceinline__ void ct_bfly_ot(uint64_t& X, uint64_t& Y, Tw a, Tw b, uint64_t q, uint64_t q2) {
-  const uint64_t x = csub(X, q2);
-  const uint64_t t = shoup(shoup(Y, a.w, a.wb, q), b.w, b.wb, q);
-  X = x + t;
-  Y = x - t + q2;
-}
+template <bool FAST>
+struct Arith;
 
-// Gentleman-Sande butterfly: X, Y in [0, 2q) -> X + Y, (X - Y) W, both in [0, 2q).
-__device__ __forceinline__ void gs_bfly(uint64_t& X, uint64_t& Y, uint64_t w, uint64_t wb, uint64_t q,
-                                        uint64_t q2) {
-  const uint64_t s = csub(X + Y, q2);
-  const uint64_t d = X - Y + q2;
-  X = s;
-  Y = shoup(d, w, wb, q);
-}
+template <>
+struct Arith<false> {
+  // b * w mod q in [0, 2q), any b < 2^64.
+  static __device__ __forceinline__ uint64_t mul(uint64_t b, const Tw& t, const Mod& m) {
+    const uint64_t qh = mulhi64(b, t.wb);
+    return b * t.w - qh * m.q;
+  }
+  // Cooley-Tukey: X, Y in [0, 4q) -> X + WY, X - WY in [0, 4q).
+  static __device__ __forceinline__ void ct(uint64_t& X, uint64_t& Y, const Tw& t, const Mod& m) {
+    const uint64_t x = csub(X, m.q2);
+    const uint64_t v = mul(Y, t, m);
+    X = x + v;
+    Y = x - v + m.q2;
+  }
+  // Same with the twiddle applied as two factors (on-the-fly twiddling, Section VII).
+  static __device__ __forceinline__ void ct2(uint64_t& X, uint64_t& Y, const Tw& a, const Tw& b, const Mod& m) {
+    const uint64_t x = csub(X, m.q2);
+    const uint64_t v = mul(mul(Y, a, m), b, m);
+    X = x + v;
+    Y = x - v + m.q2;
+  }
+  // Gentleman-Sande: X, Y in [0, 2q) -> X + Y, (X - Y) W in [0, 2q).
+  static __device__ __forceinline__ void gs(uint64_t& X, uint64_t& Y, const Tw& t, const Mod& m) {
+    const uint64_t s = csub(X + Y, m.q2);
+    const uint64_t d = X - Y + m.q2;
+    X = s;
+    Y = mul(d, t, m);
+  }
+  static __device__ __forceinline__ void gs2(uint64_t& X, uint64_t& Y, const Tw& a, const Tw& b, const Mod& m) {
+    const uint64_t s = csub(X + Y, m.q2);
+    const uint64_t d = X - Y + m.q2;
+    X = s;
+    Y = mul(mul(d, a, m), b, m);
+  }
+  // Last inverse stage with the 1/N scale: X' = (X + Y)/N, Y' = (X - Y) W/N, in [0, 2q).
+  static __device__ __forceinline__ void gs_scaled(uint64_t& X, uint64_t& Y, const Tw& wn, const Tw& n,
+                                                   const Mod& m) {
+    const uint64_t s = X + Y;
+    const uint64_t d = X - Y + m.q2;
+    X = mul(s, n, m);
+    Y = mul(d, wn, m);
+  }
+  static __device__ __forceinline__ uint64_t fwd_final(uint64_t x, const Mod& m) { return csub(csub(x, m.q2), m.q); }
+  static __device__ __forceinline__ uint64_t inv_final(uint64_t x, const Mod& m) { return csub(x, m.q); }
+};
 
-__device__ __forceinline__ void gs_bfly_ot(uint64_t& X, uint64_t& Y, Tw a, Tw b, uint64_t q, uint64_t q2) {
-  const uint64_t s = csub(X + Y, q2);
-  const uint64_t d = X - Y + q2;
-  X = s;
-  Y = shoup(shoup(d, a.w, a.wb, q), b.w, b.wb, q);
-}
-
-// Last inverse stage with the 1/N scale folded in: X' = (X + Y)/N, Y' = (X - Y) W/N,
-// both in [0, 2q); `n` holds 1/N and `wn` holds W/N, each with its companion.
-__device__ __forceinline__ void gs_bfly_scaled(uint64_t& X, uint64_t& Y, Tw wn, Tw n, uint64_t q, uint64_t q2) {
-  const uint64_t s = X + Y;
-  const uint64_t d = X - Y + q2;
-  X = shoup(s, n.w, n.wb, q);
-  Y = shoup(d, wn.w, wn.wb, q);
-}
-
-// [0, 4q) -> [0, q)
-__device__ __forceinline__ uint64_t canon4(uint64_t x, uint64_t q, uint64_t q2) { return csub(csub(x, q2), q); }
-// [0, 2q) -> [0, q)
-__device__ __forceinline__ uint64_t canon2(uint64_t x, uint64_t q) { return csub(x, q); }
+template <>
+struct Arith<true> {
+  // b * w mod q in [0, 4q), any b < 2^64 (q < 2^60).
+  static __device__ __forceinline__ uint64_t mul(uint64_t b, const Tw& t, const Mod& m) {
+    const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+    const uint32_t w0 = (uint32_t)t.w, w1 = (uint32_t)(t.w >> 32);
+    const uint32_t s0 = (uint32_t)t.wb, s1 = (uint32_t)(t.wb >> 32);
+    const uint32_t n0 = (uint32_t)m.nq, n1 = (uint32_t)(m.nq >> 32);
+    const uint32_t h1 = __umulhi(b0, s1), h2 = __umulhi(b1, s0);
+    const uint64_t qh = (uint64_t)b1 * s1 + h1 + h2;
+    const uint32_t c0 = (uint32_t)qh, c1 = (uint32_t)(qh >> 32);
+    const uint64_t lo = (uint64_t)b0 * w0 + (uint64_t)c0 * n0;
+    const uint32_t hi = (uint32_t)(lo >> 32) + b0 * w1 + b1 * w0 + c0 * n1 + c1 * n0;
+    return ((uint64_t)hi << 32) | (uint32_t)lo;
+  }
+  // Cooley-Tukey: X, Y in [0, 8q) -> X + WY, X - WY in [0, 8q).
+  static __device__ __forceinline__ void ct(uint64_t& X, uint64_t& Y, const Tw& t, const Mod& m) {
+    const uint64_t x = csub_sign(X, m.nq4);
+    const uint64_t v = mul(Y, t, m);
+    X = x + v;
+    Y = x + m.q4 - v;
+  }
+  static __device__ __forceinline__ void ct2(uint64_t& X, uint64_t& Y, const Tw& a, const Tw& b, const Mod& m) {
+    const uint64_t x = csub_sign(X, m.nq4);
+    const uint64_t v = mul(mul(Y, a, m), b, m);
+    X = x + v;
+    Y = x + m.q4 - v;
+  }
+  // Gentleman-Sande: X, Y in [0, 4q) -> X + Y, (X - Y) W in [0, 4q).
+  static __device__ __forceinline__ void gs(uint64_t& X, uint64_t& Y, const Tw& t, const Mod& m) {
+    const uint64_t s = csub_sign(X + Y, m.nq4);
+    const uint64_t d = X + m.q4 - Y;
+    X = s;
+    Y = mul(d, t, m);
+  }
+  static __device__ __forceinline__ void gs2(uint64_t& X, uint64_t& Y, const Tw& a, const Tw& b, const Mod& m) {
+    const uint64_t s = csub_sign(X + Y, m.nq4);
+    const uint64_t d = X + m.q4 - Y;
+    X = s;
+    Y = mul(mul(d, a, m), b, m);
+  }
+  static __device__ __forceinline__ void gs_scaled(uint64_t& X, uint64_t& Y, const Tw& wn, const Tw& n,
+                                                   const Mod& m) {
+    const uint64_t s = X + Y;
+    const uint64_t d = X + m.q4 - Y;
+    X = mul(s, n, m);
+    Y = mul(d, wn, m);
+  }
+  static __device__ __forceinline__ uint64_t fwd_final(uint64_t x, const Mod& m) {
+    return csub_sign(csub_sign(csub_sign(x, m.nq4), m.nq2), m.nq);
+  }
+  static __device__ __forceinline__ uint64_t inv_final(uint64_t x, const Mod& m) {
+    return csub_sign(csub_sign(x, m.nq2), m.nq);
+  }
+};
 
 // General a * b mod q for a, b < q < 2^62 (no precomputed companion): Barrett
 // reduction with s = bitlen(q), mu = floor(2^(2s) / q) < 2^(s+1).

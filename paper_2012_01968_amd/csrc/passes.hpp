@@ -34,6 +34,7 @@ struct PassArgs {
   uint32_t logN;
   uint32_t logN1;        // log2 of the column-pass size (0: single pass)
   uint32_t ot_log2_base; // log2 B
+  uint32_t fast;         // every prime below 2^60: the Arith<true> policy applies
 };
 
 template <int Begin, int End, typename F>
@@ -85,9 +86,10 @@ struct OtTables {
 // Forward (Cooley-Tukey) register step K_STEP on the R values of one lane.
 // TabFn(ix) returns the table twiddle Psi[ix]; the last OTS stages of this
 // sub-transform take their twiddles from `ot` instead.
-template <int LOGM, int LR, int K_STEP, int OTS, int NR, typename TabFn>
+template <bool FAST, int LOGM, int LR, int K_STEP, int OTS, int NR, typename TabFn>
 __device__ __forceinline__ void ct_step(uint64_t (&x)[NR], uint32_t t, uint32_t base,
-                                        TabFn&& tab, const OtTables& ot, uint64_t q, uint64_t q2) {
+                                        TabFn&& tab, const OtTables& ot, const Mod& md) {
+  using A = Arith<FAST>;
   using S = Steps<LOGM, LR>;
   static_assert(NR == S::R, "register array size");
   constexpr int lo = S::blo(K_STEP);
@@ -104,10 +106,10 @@ __device__ __forceinline__ void ct_step(uint64_t (&x)[NR], uint32_t t, uint32_t 
       if constexpr (OTS > 0 && s >= LOGM - OTS) {
         Tw a, c;
         ot.get(ix, a, c);
-        ct_bfly_ot(x[u], x[u | (1 << i)], a, c, q, q2);
+        A::ct2(x[u], x[u | (1 << i)], a, c, md);
       } else {
         const Tw w = tab(ix);
-        ct_bfly(x[u], x[u | (1 << i)], w.w, w.wb, q, q2);
+        A::ct(x[u], x[u | (1 << i)], w, md);
       }
     }
   });
@@ -116,10 +118,11 @@ __device__ __forceinline__ void ct_step(uint64_t (&x)[NR], uint32_t t, uint32_t 
 // Inverse (Gentleman-Sande) register step K_STEP: stages from the low bit up.
 // SCALE0: this sub-transform holds stage 0 of the whole transform, whose butterfly
 // also applies the 1/N scale (sc0 = 1/N, sc1 = Psi_inv[1]/N).
-template <int LOGM, int LR, int K_STEP, int OTS, bool SCALE0, int NR, typename TabFn>
+template <bool FAST, int LOGM, int LR, int K_STEP, int OTS, bool SCALE0, int NR, typename TabFn>
 __device__ __forceinline__ void gs_step(uint64_t (&x)[NR], uint32_t t, uint32_t base,
-                                        TabFn&& tab, const OtTables& ot, uint64_t q, uint64_t q2,
+                                        TabFn&& tab, const OtTables& ot, const Mod& md,
                                         const Tw& sc0, const Tw& sc1) {
+  using A = Arith<FAST>;
   using S = Steps<LOGM, LR>;
   static_assert(NR == S::R, "register array size");
   constexpr int lo = S::blo(K_STEP);
@@ -132,17 +135,17 @@ __device__ __forceinline__ void gs_step(uint64_t (&x)[NR], uint32_t t, uint32_t 
     for (int u = 0; u < S::R; ++u) {
       if (u & (1 << i)) continue;
       if constexpr (SCALE0 && s == 0) {
-        gs_bfly_scaled(x[u], x[u | (1 << i)], sc1, sc0, q, q2);
+        A::gs_scaled(x[u], x[u | (1 << i)], sc1, sc0, md);
       } else {
         const uint32_t r = S::template idx<K_STEP>(t, (uint32_t)u);
         const uint32_t ix = (base << s) + (r >> (bit + 1));
         if constexpr (OTS > 0 && s >= LOGM - OTS) {
           Tw a, c;
           ot.get(ix, a, c);
-          gs_bfly_ot(x[u], x[u | (1 << i)], a, c, q, q2);
+          A::gs2(x[u], x[u | (1 << i)], a, c, md);
         } else {
           const Tw w = tab(ix);
-          gs_bfly(x[u], x[u | (1 << i)], w.w, w.wb, q, q2);
+          A::gs(x[u], x[u | (1 << i)], w, md);
         }
       }
     }

@@ -21,7 +21,7 @@ def declared_functions():
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(LIB):
-        pytest.fail("library not built: run python -m paper_2012_01968_amd.build")
+        pytest.fail("library not built: run python paper_2012_01968_amd/build.py")
     return ctypes.CDLL(LIB)
 
 

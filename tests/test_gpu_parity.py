@@ -95,9 +95,10 @@ def test_pass_splits(logN, n1):
 
 # ------------------------------------------------------------------ edge values
 
-@pytest.mark.parametrize("bits", [31, 54, 62])
+@pytest.mark.parametrize("bits", [31, 54, 59, 60, 61, 62])
 def test_prime_widths(bits):
-    # 62-bit primes stretch the lazy ranges to their limit (4q < 2^64)
+    # primes below 2^60 take the estimated-quotient arithmetic; 61- and 62-bit primes the exact one,
+    # whose lazy ranges reach their limit (4q < 2^64) at 62 bits
     check_fwd_inv(1 << 16, 3, 2, bits, 500 + bits)
     check_fwd_inv(1 << 12, 3, 2, bits, 520 + bits, twiddle_mode=ntt.TWIDDLE_OT, ot_stages=2)
 
