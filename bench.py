@@ -89,6 +89,9 @@ def main() -> int:
     ap.add_argument("--log2-n1", type=int, default=0)
     ap.add_argument("--rotate-gib", type=float, default=1.25, help="total size of the rotating input copies")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="counter-collection driver: --steps steps of one twiddle mode (no timing, no JSON), "
+                         "then one plain device copy of a ciphertext for the counters' byte calibration")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -112,6 +115,22 @@ def main() -> int:
     torch.cuda.synchronize()
     log(f"workload N={N} L={L} P={P}: {ct_bytes/1e6:.1f} MB per ciphertext, {R} rotating copies "
         f"({R*ct_bytes/2**30:.2f} GiB)")
+
+    if args.profile_run:
+        mode = "ot" if args.twiddle == "auto" else args.twiddle
+        kw = dict(log2_n1=args.log2_n1)
+        if mode == "ot":
+            kw.update(twiddle_mode=ntt.TWIDDLE_OT, ot_stages=2)
+        plan = ntt.ntt_plan_create(N, primes, **kw)
+        for i in range(args.steps):
+            ntt.ntt_forward(plan, bufs[i % R])
+            ntt.ntt_inverse(plan, bufs[i % R])
+        torch.cuda.synchronize()
+        bufs[R - 1].copy_(bufs[1])        # calibration: one plain copy of ct_bytes read + ct_bytes written
+        torch.cuda.synchronize()
+        plan.destroy()
+        log(f"profile run: {args.steps} steps ({mode}) + one {ct_bytes}-byte device copy")
+        return 0
 
     modes = ["table", "ot"] if args.twiddle == "auto" else [args.twiddle]
     results = {}
