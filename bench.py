@@ -72,6 +72,8 @@ def twiddle_bytes(pass_kind: str, N: int, L: int, log2_n1: int, ots: int, b: int
     N1 = 1 << log2_n1
     if pass_kind == "col":
         return 16 * L * N1
+    if pass_kind == "fused":
+        return twiddle_bytes("col", N, L, log2_n1, ots, b) + twiddle_bytes("row", N, L, log2_n1, ots, b)
     if log2_n1 == 0:
         N1 = 1
     table = N // (1 << ots) - N1
@@ -79,13 +81,27 @@ def twiddle_bytes(pass_kind: str, N: int, L: int, log2_n1: int, ots: int, b: int
     return 16 * L * (table + ot)
 
 
+def data_bytes(pass_kind: str, N: int, L: int, P: int) -> int:
+    """Algorithmic data bytes of one launch: every pass reads and writes each residue once."""
+    return (2 if pass_kind == "fused" else 1) * 16 * P * L * N
+
+
+VARIANTS = {   # name -> plan options (twiddle source x kernel path)
+    "table-split": dict(kernel_path=1),
+    "ot-split": dict(kernel_path=1, twiddle_mode=2, ot_stages=2),
+    "table-fused": dict(kernel_path=2),
+    "ot-fused": dict(kernel_path=2, twiddle_mode=2, ot_stages=2),
+}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--twiddle", choices=["auto", "table", "ot"], default="auto",
-                    help="auto measures both twiddle modes and reports the faster")
+    ap.add_argument("--variant", choices=["auto"] + list(VARIANTS), default="auto",
+                    help="auto measures every variant (table / OT twiddles x split / fused launch) and reports "
+                         "the fastest")
     ap.add_argument("--log2-n1", type=int, default=0)
     ap.add_argument("--rotate-gib", type=float, default=1.25, help="total size of the rotating input copies")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -117,11 +133,8 @@ def main() -> int:
         f"({R*ct_bytes/2**30:.2f} GiB)")
 
     if args.profile_run:
-        mode = "ot" if args.twiddle == "auto" else args.twiddle
-        kw = dict(log2_n1=args.log2_n1)
-        if mode == "ot":
-            kw.update(twiddle_mode=ntt.TWIDDLE_OT, ot_stages=2)
-        plan = ntt.ntt_plan_create(N, primes, **kw)
+        mode = "ot-fused" if args.variant == "auto" else args.variant
+        plan = ntt.ntt_plan_create(N, primes, log2_n1=args.log2_n1, **VARIANTS[mode])
         for i in range(args.steps):
             ntt.ntt_forward(plan, bufs[i % R])
             ntt.ntt_inverse(plan, bufs[i % R])
@@ -132,15 +145,13 @@ def main() -> int:
         log(f"profile run: {args.steps} steps ({mode}) + one {ct_bytes}-byte device copy")
         return 0
 
-    modes = ["table", "ot"] if args.twiddle == "auto" else [args.twiddle]
+    modes = list(VARIANTS) if args.variant == "auto" else [args.variant]
     results = {}
     for mode in modes:
-        kw = dict(log2_n1=args.log2_n1)
-        if mode == "ot":
-            kw.update(twiddle_mode=ntt.TWIDDLE_OT, ot_stages=2)
-        plan = ntt.ntt_plan_create(N, primes, **kw)
+        plan = ntt.ntt_plan_create(N, primes, log2_n1=args.log2_n1, **VARIANTS[mode])
         info = ntt.ntt_plan_get_info(plan)
         npass = ntt.ntt_plan_num_passes(plan)
+        fused = info["kernel_path"] == ntt.PATH_FUSED
 
         def step(i):
             b = bufs[i % R]
@@ -163,8 +174,11 @@ def main() -> int:
         ms = total_ms / args.steps
 
         # per-kernel durations: the same steps with an event between consecutive kernels
-        names = ([f"fwd_col", "fwd_row"] if npass == 2 else ["fwd_row"]) + \
-                (["inv_row", "inv_col"] if npass == 2 else ["inv_row"])
+        if fused:
+            names = ["fwd_fused", "inv_fused"]
+        else:
+            names = (["fwd_col", "fwd_row"] if npass == 2 else ["fwd_row"]) + \
+                    (["inv_row", "inv_col"] if npass == 2 else ["inv_row"])
         K = args.steps
         kev = [[torch.cuda.Event(enable_timing=True) for _ in range(2 * npass + 1)] for _ in range(K)]
         for i in range(K):
@@ -209,15 +223,14 @@ def main() -> int:
     best = min(results, key=lambda m: results[m]["ms"])
     r = results[best]
     info = r["info"]
-    ots = info["ot_stages"] if best == "ot" else 0
+    ots = info["ot_stages"] if best.startswith("ot") else 0
     n_limb_ntts = 2 * P * L
     value = n_limb_ntts / (r["ms"] * 1e-3)
 
     # roofline of the dominant kernel
     dom = max(r["kms"], key=r["kms"].get)
-    kind = "col" if dom.endswith("col") else "row"
-    data_bytes = 16 * P * L * N
-    alg_bytes = data_bytes + twiddle_bytes(kind, N, L, info["log2_n1"], ots)
+    kind = dom.split("_")[1]
+    alg_bytes = data_bytes(kind, N, L, P) + twiddle_bytes(kind, N, L, info["log2_n1"], ots)
     achieved = alg_bytes / (r["kms"][dom] * 1e-3) / 1e9
     src_hash = kernel_source_hash()
     traffic = read_traffic(f"{best}:{dom}", src_hash)
@@ -225,7 +238,7 @@ def main() -> int:
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "kernel_us": round(r["kms"][dom] * 1e3, 2), "alg_bytes_per_launch": alg_bytes}
     step_bytes = 2 * sum(16 * P * L * N + twiddle_bytes(k, N, L, info["log2_n1"], ots)
-                         for k in (["col", "row"] if r["npass"] == 2 else ["row"]))
+                         for k in (["col", "row"] if info["log2_n1"] else ["row"]))
     step_frac = step_bytes / (r["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS
 
     cpu = None
@@ -239,7 +252,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": "one ciphertext, N=2^16, L=45 primes in [2^59,2^60) (seed 2), 2 polys, "
                                "forward NTT then inverse NTT (180 limb-NTTs per step)",
-                   "N": N, "L": L, "polys": P, "twiddle": best, "ot_stages": ots,
+                   "N": N, "L": L, "polys": P, "variant": best, "ot_stages": ots,
                    "log2_n1": info["log2_n1"], "rotating_copies": R},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -70,8 +70,19 @@ typedef struct {
     int32_t ot_log2_base;   /* log2 of the OT digit base; 0 = 10 (base 1024)            */
     int32_t log2_n1;        /* size of the first (column) pass, N = N1 * N2; 0 = auto;  */
                             /* -1 forces the single-pass kernel where N allows it       */
-    int32_t reserved[4];    /* must be zero                                             */
+    int32_t kernel_path;    /* NTT_PATH_*: how the two passes are launched               */
+    int32_t reserved[3];    /* must be zero                                             */
 } ntt_plan_opts;
+
+/* Kernel paths for two-pass plans.  SPLIT launches the column pass and the row pass as
+ * two kernels.  FUSED runs both in one persistent launch whose workgroups drain
+ * per-XCD queues of tiles, so the pass-1 output of a limb is read back from that XCD's L2
+ * (Section VI-C's two kernels, scheduled for gfx950's eight L2 slices); it needs every
+ * prime below 2^60 and N1 x N2 one of 2^6 x 2^7, 2^7 x 2^7, 2^7 x 2^8, 2^8 x 2^8, 2^8 x 2^9.
+ * AUTO takes SPLIT (measured faster on MI355X).  Launches of one FUSED plan share a small counter
+ * block, so the library orders them across streams (a launch on another stream waits for
+ * the previous one). */
+enum { NTT_PATH_AUTO = 0, NTT_PATH_SPLIT = 1, NTT_PATH_FUSED = 2 };
 
 /* Create a plan for length-N transforms over L primes (Section III-B; Algorithm 1
  * REQUIRE: each q = 1 mod 2N).  `primes` is a host array of L distinct primes with
@@ -91,9 +102,11 @@ ntt_status ntt_plan_destroy(ntt_plan_t plan);
 /* Copy the L roots psi_l in use into the host array psi_out (L entries). */
 ntt_status ntt_plan_get_roots(ntt_plan_t plan, uint64_t* psi_out);
 
-/* N, L and the pass split chosen by the plan (any pointer may be NULL). */
+/* N, L, the pass split, twiddle mode, OT stages and kernel path (NTT_PATH_SPLIT or
+ * NTT_PATH_FUSED; single-pass plans report SPLIT) chosen by the plan.  Any pointer may be
+ * NULL. */
 ntt_status ntt_plan_get_info(ntt_plan_t plan, uint32_t* N, uint32_t* L, uint32_t* log2_n1,
-                             int32_t* twiddle_mode, int32_t* ot_stages);
+                             int32_t* twiddle_mode, int32_t* ot_stages, int32_t* kernel_path);
 
 /* In-place forward NTT of every vector of d_data ([n_polys][L][N] uint64, device).
  * Section III-A merged-twist transform computed as Algorithm 1 (Cooley-Tukey with the
@@ -104,17 +117,18 @@ ntt_status ntt_forward(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, void
 /* One kernel of the forward transform, for callers that schedule or time the passes
  * themselves (Section VI-C's Kernel-1 / Kernel-2).  pass 0 runs the column pass (the
  * first log2 N1 stages), pass 1 the row pass (the remaining stages, final reduction,
- * bit-reversed output).  A single-pass plan (log2_n1 = 0) has only pass 0.  Running
+ * bit-reversed output).  A single-pass or fused plan has only pass 0.  Running
  * every pass in order equals ntt_forward.  Errors: NTT_ERR_ARG for a pass index at or
  * above ntt_plan_num_passes. */
 ntt_status ntt_forward_pass(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, uint32_t pass, void* stream);
 
 /* One kernel of the inverse transform: pass 0 runs the row pass (the first
  * Gentleman-Sande stages), pass 1 the column pass (the last stages with the 1/N scale).
- * A single-pass plan has only pass 0.  Running every pass in order equals ntt_inverse. */
+ * A single-pass or fused plan has only pass 0.  Running every pass in order equals
+ * ntt_inverse. */
 ntt_status ntt_inverse_pass(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, uint32_t pass, void* stream);
 
-/* Number of kernels per transform for this plan: 1 (single pass) or 2. */
+/* Number of kernels per transform for this plan: 1 (single pass or fused) or 2. */
 uint32_t ntt_plan_num_passes(ntt_plan_t plan);
 
 /* In-place inverse: takes bit-reversed NTT-domain vectors and returns natural-order

@@ -18,10 +18,11 @@ __all__ = [
     "NttError", "Plan", "ntt_plan_create", "ntt_plan_destroy", "ntt_plan_get_roots", "ntt_plan_get_info",
     "ntt_forward", "ntt_inverse", "ntt_forward_pass", "ntt_inverse_pass", "ntt_plan_num_passes",
     "ntt_pointwise_mul", "ntt_polymul_negacyclic", "ntt_status_string",
-    "library_path", "TWIDDLE_AUTO", "TWIDDLE_TABLE", "TWIDDLE_OT",
+    "library_path", "TWIDDLE_AUTO", "TWIDDLE_TABLE", "TWIDDLE_OT", "PATH_AUTO", "PATH_SPLIT", "PATH_FUSED",
 ]
 
 TWIDDLE_AUTO, TWIDDLE_TABLE, TWIDDLE_OT = 0, 1, 2
+PATH_AUTO, PATH_SPLIT, PATH_FUSED = 0, 1, 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libntt_mi355x.so")
@@ -40,7 +41,7 @@ _lib = ctypes.CDLL(_LIB_PATH)
 class _Opts(ctypes.Structure):
     _fields_ = [("twiddle_mode", ctypes.c_int32), ("ot_stages", ctypes.c_int32),
                 ("ot_log2_base", ctypes.c_int32), ("log2_n1", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("kernel_path", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 _vp = ctypes.c_void_p
@@ -50,7 +51,8 @@ _lib.ntt_plan_create.argtypes = [ctypes.POINTER(_vp), _u32, _u64p, _u32, ctypes.
 _lib.ntt_plan_destroy.argtypes = [_vp]
 _lib.ntt_plan_get_roots.argtypes = [_vp, _u64p]
 _lib.ntt_plan_get_info.argtypes = [_vp, ctypes.POINTER(_u32), ctypes.POINTER(_u32), ctypes.POINTER(_u32),
-                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.POINTER(ctypes.c_int32)]
 _lib.ntt_forward.argtypes = [_vp, _vp, _u32, _vp]
 _lib.ntt_inverse.argtypes = [_vp, _vp, _u32, _vp]
 _lib.ntt_forward_pass.argtypes = [_vp, _vp, _u32, _u32, _vp]
@@ -132,10 +134,10 @@ def _polys(plan: Plan, buf, n_polys) -> int:
 
 
 def ntt_plan_create(N: int, primes, *, twiddle_mode: int = 0, ot_stages: int = 0, ot_log2_base: int = 0,
-                    log2_n1: int = 0) -> Plan:
+                    log2_n1: int = 0, kernel_path: int = 0) -> Plan:
     primes = [int(q) for q in primes]
     arr = (ctypes.c_uint64 * len(primes))(*primes)
-    opts = _Opts(twiddle_mode, ot_stages, ot_log2_base, log2_n1)
+    opts = _Opts(twiddle_mode, ot_stages, ot_log2_base, log2_n1, kernel_path)
     h = _vp()
     _check(_lib.ntt_plan_create(ctypes.byref(h), N, arr, len(primes), ctypes.byref(opts)), "ntt_plan_create")
     return Plan(h.value, N, len(primes))
@@ -153,10 +155,11 @@ def ntt_plan_get_roots(plan: Plan) -> list[int]:
 
 def ntt_plan_get_info(plan: Plan) -> dict:
     N, L, n1 = _u32(), _u32(), _u32()
-    mode, ots = ctypes.c_int32(), ctypes.c_int32()
+    mode, ots, path = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     _check(_lib.ntt_plan_get_info(plan.handle, ctypes.byref(N), ctypes.byref(L), ctypes.byref(n1),
-                                  ctypes.byref(mode), ctypes.byref(ots)), "ntt_plan_get_info")
-    return {"N": N.value, "L": L.value, "log2_n1": n1.value, "twiddle_mode": mode.value, "ot_stages": ots.value}
+                                  ctypes.byref(mode), ctypes.byref(ots), ctypes.byref(path)), "ntt_plan_get_info")
+    return {"N": N.value, "L": L.value, "log2_n1": n1.value, "twiddle_mode": mode.value, "ot_stages": ots.value,
+            "kernel_path": path.value}
 
 
 def ntt_forward(plan: Plan, data, n_polys: int | None = None, stream=None) -> None:

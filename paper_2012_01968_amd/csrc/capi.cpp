@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -66,6 +67,14 @@ struct ntt_plan_s {
   int32_t twiddle_mode = NTT_TWIDDLE_TABLE;
   int32_t ot_stages = 0;
   uint32_t ot_log2_base = 10;
+  int32_t kernel_path = NTT_PATH_SPLIT;   // SPLIT or FUSED after creation
+  uint32_t fused_lag = 4;                 // vectors an XCD queue runs pass 1 ahead of pass 2
+  uint32_t fused_grid = 1024;             // persistent workgroups (4 per CU)
+  uint32_t* d_ctr = nullptr;              // fused-launch counters: 16 + kMaxFusedVectors words
+  std::mutex fused_mu;                    // orders fused launches of this plan across streams
+  hipEvent_t fused_ev = nullptr;
+  hipStream_t fused_last = nullptr;
+  bool fused_pending = false;
   int device = 0;
   bool fast = false;  // all primes below 2^60 (wider lazy ranges, estimated quotients)
   std::vector<uint64_t> primes, psis;
@@ -93,8 +102,12 @@ struct ntt_plan_s {
       (void)hipEventSynchronize(scratch_ev);
       (void)hipEventDestroy(scratch_ev);
     }
+    if (fused_ev) {
+      (void)hipEventSynchronize(fused_ev);
+      (void)hipEventDestroy(fused_ev);
+    }
     void* ptrs[] = {d_q, d_tw_fwd, d_tw_inv, d_ot_lo_fwd, d_ot_hi_fwd, d_ot_lo_inv, d_ot_hi_inv,
-                    d_scale, d_mu, d_bits, scratch};
+                    d_scale, d_mu, d_bits, scratch, d_ctr};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
   }
@@ -116,6 +129,10 @@ struct ntt_plan_s {
     return a;
   }
   int active_ot() const { return twiddle_mode == NTT_TWIDDLE_OT ? ot_stages : 0; }
+  bool fused_for(uint32_t n_polys) const {
+    return kernel_path == NTT_PATH_FUSED && (uint64_t)n_polys * L <= kMaxFusedVectors;
+  }
+  static constexpr uint64_t kMaxFusedVectors = 1u << 16;
 };
 
 static ntt_status build_plan(ntt_plan_s* p, uint32_t N, const uint64_t* primes, uint32_t L,
@@ -130,6 +147,7 @@ static ntt_status build_plan(ntt_plan_s* p, uint32_t N, const uint64_t* primes, 
   if (opts) o = *opts;
   for (int32_t r : o.reserved)
     if (r != 0) return fail(NTT_ERR_ARG, "reserved option fields must be zero");
+  if (o.kernel_path < 0 || o.kernel_path > 2) return fail(NTT_ERR_ARG, "kernel_path out of range");
   if (o.twiddle_mode < 0 || o.twiddle_mode > 2) return fail(NTT_ERR_ARG, "twiddle_mode out of range");
   if (o.ot_stages < 0 || o.ot_stages > 2) return fail(NTT_ERR_ARG, "ot_stages must be 0, 1 or 2");
   if (o.ot_log2_base < 0 || o.ot_log2_base > 16) return fail(NTT_ERR_ARG, "ot_log2_base out of range");
@@ -167,6 +185,16 @@ static ntt_status build_plan(ntt_plan_s* p, uint32_t N, const uint64_t* primes, 
   }
 
   p->fast = *std::max_element(p->primes.begin(), p->primes.end()) < (1ull << 60);
+  {
+    const bool can_fuse = p->fast && p->logN1 != 0 && nttk::fused_supported(p->logN, p->logN1, p->active_ot());
+    if (o.kernel_path == NTT_PATH_FUSED && !can_fuse)
+      return fail(NTT_ERR_UNSUPPORTED, "the fused path needs primes below 2^60 and a built N1 x N2 shape");
+    // AUTO takes the split path: on gfx950 the pass-1 output of a split launch already round-trips
+    // through the Infinity Cache, and the fused queue measured slower (see the design notes).
+    p->kernel_path = (o.kernel_path == NTT_PATH_FUSED && can_fuse) ? NTT_PATH_FUSED : NTT_PATH_SPLIT;
+    if (const char* e = std::getenv("NTT_FUSED_LAG")) p->fused_lag = (uint32_t)std::max(1, std::atoi(e));
+    if (const char* e = std::getenv("NTT_FUSED_GRID")) p->fused_grid = (uint32_t)std::max(1, std::atoi(e));
+  }
 
   // ---- tables (host), one worker per block of limbs
   const size_t NN = N;
@@ -247,7 +275,37 @@ static ntt_status build_plan(ntt_plan_s* p, uint32_t N, const uint64_t* primes, 
   }
   if ((e = hipEventCreateWithFlags(&p->scratch_ev, hipEventDisableTiming)) != hipSuccess)
     return hip_fail(e, "hipEventCreate");
+  if (p->kernel_path == NTT_PATH_FUSED) {
+    const size_t words = 16 + ntt_plan_s::kMaxFusedVectors;
+    if ((e = hipMalloc(reinterpret_cast<void**>(&p->d_ctr), words * sizeof(uint32_t))) != hipSuccess)
+      return e == hipErrorOutOfMemory ? fail(NTT_ERR_NOMEM, "counter allocation failed") : hip_fail(e, "hipMalloc");
+    if ((e = hipMemset(p->d_ctr, 0, words * sizeof(uint32_t))) != hipSuccess) return hip_fail(e, "hipMemset");
+    if ((e = hipEventCreateWithFlags(&p->fused_ev, hipEventDisableTiming)) != hipSuccess)
+      return hip_fail(e, "hipEventCreate");
+  }
   return NTT_OK;
+}
+
+// Both passes in one persistent launch.  Launches of one plan share its counter block, so a
+// launch on a stream other than the previous one waits for that previous launch.
+static hipError_t launch_fused(ntt_plan_t plan, uint64_t* data, uint32_t n_polys, bool inverse, hipStream_t st) {
+  std::lock_guard<std::mutex> lk(plan->fused_mu);
+  hipError_t e;
+  if (plan->fused_pending && plan->fused_last != st && (e = hipStreamWaitEvent(st, plan->fused_ev, 0)) != hipSuccess)
+    return e;
+  e = nttk::launch_fused(plan->args(data, n_polys, inverse), plan->active_ot(), inverse, plan->d_ctr, n_polys,
+                         plan->fused_lag, plan->fused_grid, st);
+  if (e != hipSuccess) return e;
+  if ((e = hipEventRecord(plan->fused_ev, st)) != hipSuccess) return e;
+  plan->fused_last = st;
+  plan->fused_pending = true;
+  return hipSuccess;
+}
+
+static hipError_t transform(ntt_plan_t plan, uint64_t* data, uint32_t n_polys, bool inverse, hipStream_t st) {
+  if (plan->fused_for(n_polys)) return launch_fused(plan, data, n_polys, inverse, st);
+  const PassArgs a = plan->args(data, n_polys, inverse);
+  return inverse ? nttk::launch_inverse(a, plan->active_ot(), st) : nttk::launch_forward(a, plan->active_ot(), st);
 }
 
 static ntt_status check_data(ntt_plan_t plan, const void* ptr, uint32_t n_polys) {
@@ -303,13 +361,14 @@ ntt_status ntt_plan_get_roots(ntt_plan_t plan, uint64_t* psi_out) {
 }
 
 ntt_status ntt_plan_get_info(ntt_plan_t plan, uint32_t* N, uint32_t* L, uint32_t* log2_n1, int32_t* twiddle_mode,
-                             int32_t* ot_stages) {
+                             int32_t* ot_stages, int32_t* kernel_path) {
   if (!plan) return fail(NTT_ERR_ARG, "plan is NULL");
   if (N) *N = plan->N;
   if (L) *L = plan->L;
   if (log2_n1) *log2_n1 = plan->logN1;
   if (twiddle_mode) *twiddle_mode = plan->twiddle_mode;
   if (ot_stages) *ot_stages = plan->ot_stages;
+  if (kernel_path) *kernel_path = plan->kernel_path;
   return NTT_OK;
 }
 
@@ -319,15 +378,16 @@ ntt_status ntt_forward(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, void
     if (s != NTT_OK) return s;
     DeviceGuard g(plan->device);
     if (!g.ok) return fail(NTT_ERR_HIP, "cannot select the plan's device");
-    const hipError_t e = nttk::launch_forward(plan->args(d_data, n_polys, false), plan->active_ot(),
-                                              static_cast<hipStream_t>(stream));
+    const hipError_t e = transform(plan, d_data, n_polys, false, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? NTT_OK : hip_fail(e, "ntt_forward launch");
   } catch (...) {
     return fail(NTT_ERR_ARG, "unexpected failure in ntt_forward");
   }
 }
 
-uint32_t ntt_plan_num_passes(ntt_plan_t plan) { return plan ? (plan->logN1 ? 2u : 1u) : 0u; }
+uint32_t ntt_plan_num_passes(ntt_plan_t plan) {
+  return plan ? ((plan->logN1 && plan->kernel_path != NTT_PATH_FUSED) ? 2u : 1u) : 0u;
+}
 
 static ntt_status run_pass(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, uint32_t pass, void* stream,
                            bool inverse) {
@@ -339,8 +399,14 @@ static ntt_status run_pass(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, 
     if (!g.ok) return fail(NTT_ERR_HIP, "cannot select the plan's device");
     const PassArgs a = plan->args(d_data, n_polys, inverse);
     const hipStream_t st = static_cast<hipStream_t>(stream);
-    const hipError_t e = inverse ? nttk::launch_inverse_pass(a, plan->active_ot(), (int)pass, st)
-                                 : nttk::launch_forward_pass(a, plan->active_ot(), (int)pass, st);
+    hipError_t e;
+    if (plan->kernel_path == NTT_PATH_FUSED) {
+      if (!plan->fused_for(n_polys)) return fail(NTT_ERR_ARG, "batch too large for the fused path's counters");
+      e = launch_fused(plan, d_data, n_polys, inverse, st);
+    } else {
+      e = inverse ? nttk::launch_inverse_pass(a, plan->active_ot(), (int)pass, st)
+                  : nttk::launch_forward_pass(a, plan->active_ot(), (int)pass, st);
+    }
     return e == hipSuccess ? NTT_OK : hip_fail(e, "pass launch");
   } catch (...) {
     return fail(NTT_ERR_ARG, "unexpected failure in a pass launch");
@@ -361,8 +427,7 @@ ntt_status ntt_inverse(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, void
     if (s != NTT_OK) return s;
     DeviceGuard g(plan->device);
     if (!g.ok) return fail(NTT_ERR_HIP, "cannot select the plan's device");
-    const hipError_t e = nttk::launch_inverse(plan->args(d_data, n_polys, true), plan->active_ot(),
-                                              static_cast<hipStream_t>(stream));
+    const hipError_t e = transform(plan, d_data, n_polys, true, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? NTT_OK : hip_fail(e, "ntt_inverse launch");
   } catch (...) {
     return fail(NTT_ERR_ARG, "unexpected failure in ntt_inverse");
@@ -422,11 +487,12 @@ ntt_status ntt_polymul_negacyclic(ntt_plan_t plan, const uint64_t* d_a, const ui
     if ((e = hipMemcpyAsync(tmp, d_b, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess)
       return hip_fail(e, "copying b");
     const int ot = plan->active_ot();
-    if ((e = nttk::launch_forward(plan->args(d_c, n_polys, false), ot, st)) != hipSuccess ||
-        (e = nttk::launch_forward(plan->args(tmp, n_polys, false), ot, st)) != hipSuccess ||
+    (void)ot;
+    if ((e = transform(plan, d_c, n_polys, false, st)) != hipSuccess ||
+        (e = transform(plan, tmp, n_polys, false, st)) != hipSuccess ||
         (e = nttk::launch_pointwise(d_c, tmp, d_c, plan->d_q, plan->d_mu, plan->d_bits,
                                     (uint64_t)n_polys * plan->L * plan->N, plan->logN, plan->L, st)) != hipSuccess ||
-        (e = nttk::launch_inverse(plan->args(d_c, n_polys, true), ot, st)) != hipSuccess)
+        (e = transform(plan, d_c, n_polys, true, st)) != hipSuccess)
       return hip_fail(e, "ntt_polymul_negacyclic launch");
     if ((e = hipEventRecord(plan->scratch_ev, st)) != hipSuccess) return hip_fail(e, "recording scratch event");
     plan->scratch_pending = true;

@@ -1,6 +1,7 @@
 // NTT launch entry points (host) and the element-wise product kernel.
 #include "kernels.hpp"
 #include "passes.hpp"
+#include "fused_args.hpp"
 
 namespace nttk {
 
@@ -73,6 +74,29 @@ hipError_t launch_inverse(const PassArgs& a, int ots, hipStream_t st) {
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+template <bool INV>
+hipError_t fused_dispatch(const FusedArgs& f, int ots, uint32_t max_grid, hipStream_t st);
+extern template hipError_t fused_dispatch<false>(const FusedArgs&, int, uint32_t, hipStream_t);
+extern template hipError_t fused_dispatch<true>(const FusedArgs&, int, uint32_t, hipStream_t);
+
+bool fused_supported(uint32_t logN, uint32_t logN1, int ots) {
+  if (ots < 0 || ots > 2) return false;
+  const uint32_t n2 = logN - logN1;
+  return (logN1 == 6 && n2 == 7) || (logN1 == 7 && n2 == 7) || (logN1 == 7 && n2 == 8) ||
+         (logN1 == 8 && n2 == 8) || (logN1 == 8 && n2 == 9);
+}
+
+hipError_t launch_fused(const PassArgs& a, int ots, bool inverse, uint32_t* ctr, uint32_t n_polys, uint32_t lag,
+                        uint32_t max_grid, hipStream_t st) {
+  if (!a.fast || !fused_supported(a.logN, a.logN1, ots)) return hipErrorInvalidValue;
+  FusedArgs f;
+  f.a = a;
+  f.ctr = ctr;
+  f.P = n_polys;
+  f.lag = lag;
+  return inverse ? fused_dispatch<true>(f, ots, max_grid, st) : fused_dispatch<false>(f, ots, max_grid, st);
 }
 
 hipError_t launch_pointwise(const uint64_t* A, const uint64_t* B, uint64_t* Cc, const uint64_t* qs,

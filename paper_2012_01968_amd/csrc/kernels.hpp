@@ -19,6 +19,12 @@ hipError_t launch_inverse(const PassArgs& a, int ot_stages, hipStream_t st);
 hipError_t launch_forward_pass(const PassArgs& a, int ot_stages, int pass, hipStream_t st);
 hipError_t launch_inverse_pass(const PassArgs& a, int ot_stages, int pass, hipStream_t st);
 
+// Fused single-launch transform (both passes, XCD-local queues); see fused.hpp.
+struct FusedArgs;
+bool fused_supported(uint32_t logN, uint32_t logN1, int ot_stages);
+hipError_t launch_fused(const PassArgs& a, int ot_stages, bool inverse, uint32_t* ctr, uint32_t n_polys,
+                        uint32_t lag, uint32_t max_grid, hipStream_t st);
+
 // C = A * B mod q_l element-wise over n_elems elements of a [n_vec][N] batch.
 hipError_t launch_pointwise(const uint64_t* A, const uint64_t* B, uint64_t* C, const uint64_t* qs,
                             const uint64_t* mus, const uint32_t* bits, uint64_t n_elems, uint32_t logN,

@@ -51,7 +51,7 @@ def test_status_strings(lib):
 class _Opts(ctypes.Structure):
     _fields_ = [("twiddle_mode", ctypes.c_int32), ("ot_stages", ctypes.c_int32),
                 ("ot_log2_base", ctypes.c_int32), ("log2_n1", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("kernel_path", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 def _create(lib, N, primes, opts=None):
@@ -82,6 +82,10 @@ def test_argument_errors_are_synchronous(lib):
     assert _create(lib, 1 << 10, [q], o) == (-6, None)             # OT base must be below N
     o = _Opts(0, 0, 0, 11)
     assert _create(lib, 1 << 16, [q], o) == (-6, None)             # no column pass of 2^11
+    o = _Opts(0, 0, 0, 0, 3)
+    assert _create(lib, 1 << 16, [q], o) == (-1, None)             # kernel_path out of range
+    o = _Opts(0, 0, 0, 9, 2)
+    assert _create(lib, 1 << 16, [q], o) == (-6, None)             # no fused 2^9 x 2^7 shape
     lib.ntt_forward.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p]
     lib.ntt_forward.restype = ctypes.c_int
     assert lib.ntt_forward(None, None, 1, None) == -1

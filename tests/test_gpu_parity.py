@@ -89,8 +89,67 @@ def test_ot_small_bases(logN, base):
 @pytest.mark.parametrize("logN,n1", [(13, -1), (13, 4), (13, 9), (14, 4), (14, 10), (15, 5), (16, 4), (16, 6),
                                      (16, 7), (16, 9), (16, 10), (17, 4), (17, 7), (17, 9), (17, 10)])
 def test_pass_splits(logN, n1):
-    check_fwd_inv(1 << logN, 2, 2, 60, 400 + logN, log2_n1=n1)
-    check_fwd_inv(1 << logN, 2, 1, 60, 450 + logN, log2_n1=n1, twiddle_mode=ntt.TWIDDLE_OT, ot_stages=2)
+    check_fwd_inv(1 << logN, 2, 2, 60, 400 + logN, log2_n1=n1, kernel_path=ntt.PATH_SPLIT)
+    check_fwd_inv(1 << logN, 2, 1, 60, 450 + logN, log2_n1=n1, twiddle_mode=ntt.TWIDDLE_OT, ot_stages=2,
+                  kernel_path=ntt.PATH_SPLIT)
+
+
+# ------------------------------------------------------------------ fused single-launch path
+
+@pytest.mark.parametrize("logN", [13, 14, 15, 16, 17])
+@pytest.mark.parametrize("ots", [0, 1, 2])
+def test_fused_shapes(logN, ots):
+    """Both passes in one persistent launch, per-XCD queues (default split of every fused N)."""
+    kw = dict(kernel_path=ntt.PATH_FUSED)
+    if ots:
+        kw.update(twiddle_mode=ntt.TWIDDLE_OT, ot_stages=ots)
+    # 11 limbs x 3 polys: uneven queues across the 8 XCDs (limbs 0-2 give XCDs two limbs)
+    check_fwd_inv(1 << logN, 11, 3, 60, 900 + logN + 10 * ots, **kw)
+
+
+@pytest.mark.parametrize("grid,lag", [(1, 4), (3, 1), (8, 2), (24, 100), (1024, 1)])
+def test_fused_grids_and_lags(grid, lag, monkeypatch):
+    """Tiny grids leave XCDs without workgroups (their queues are drained by the last
+    workgroup out); any lag keeps the order; repeated launches reuse the reset counters."""
+    monkeypatch.setenv("NTT_FUSED_GRID", str(grid))
+    monkeypatch.setenv("NTT_FUSED_LAG", str(lag))
+    N, L, P = 1 << 14, 9, 2
+    primes, psis, data = make(N, L, P, 60, 950 + grid)
+    plan = ntt.ntt_plan_create(N, primes, kernel_path=ntt.PATH_FUSED)
+    try:
+        assert ntt.ntt_plan_get_info(plan)["kernel_path"] == ntt.PATH_FUSED
+        want = oracle.forward(data, primes, psis, THREADS)
+        d = dev(data)
+        for _ in range(3):
+            ntt.ntt_forward(plan, d)
+            torch.cuda.synchronize()
+            assert np.array_equal(host(d), want)
+            ntt.ntt_inverse(plan, d)
+            torch.cuda.synchronize()
+            assert np.array_equal(host(d), data)
+    finally:
+        plan.destroy()
+
+
+def test_fused_and_split_agree_across_streams():
+    N, L, P = 1 << 16, 6, 2
+    primes, psis, data = make(N, L, P, 60, 990)
+    fused = ntt.ntt_plan_create(N, primes, kernel_path=ntt.PATH_FUSED)
+    split = ntt.ntt_plan_create(N, primes, kernel_path=ntt.PATH_SPLIT)
+    try:
+        want = oracle.forward(data, primes, psis, THREADS)
+        s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+        d1, d2, d3 = dev(data), dev(data), dev(data)
+        torch.cuda.synchronize()
+        ntt.ntt_forward(fused, d1, stream=s1)
+        ntt.ntt_forward(fused, d2, stream=s2)     # same plan, other stream: ordered by the library
+        ntt.ntt_forward(split, d3, stream=s2)
+        torch.cuda.synchronize()
+        for d in (d1, d2, d3):
+            assert np.array_equal(host(d), want)
+    finally:
+        fused.destroy()
+        split.destroy()
 
 
 # ------------------------------------------------------------------ edge values
