@@ -148,6 +148,49 @@ ntt_status ntt_pointwise_mul(ntt_plan_t plan, const uint64_t* d_a, const uint64_
 ntt_status ntt_polymul_negacyclic(ntt_plan_t plan, const uint64_t* d_a, const uint64_t* d_b, uint64_t* d_c,
                                   uint32_t n_polys, void* stream);
 
+/* ---------------------------------------------------------------- batches of uneven jobs
+ *
+ * Many polynomials of different N and limb counts (Section VI-A's batching, taken to
+ * uneven sizes).  A job names a plan and a device array [n_polys][n_limbs][N] whose limb l
+ * is reduced mod the plan's prime l: n_limbs may be any prefix 1..L of the plan's primes,
+ * so one plan over a long prime chain serves every limb count.  A batch object validates
+ * the jobs once and uploads per-vector descriptors; runs then enqueue the work:
+ *
+ *   NTT_BATCH_PLAIN    one ntt_forward / ntt_inverse call per job (the baseline);
+ *   NTT_BATCH_GROUPED  one launch per pass over every vector of every job sharing a plan
+ *                      (vector-list launches: all forward work first, then all inverse work);
+ *   NTT_BATCH_GRAPH    the GROUPED launches captured once into a hipGraph (on a stream the
+ *                      batch owns) and replayed on the caller's stream on every run.
+ *
+ * Jobs with NTT_OP_FORWARD_INVERSE run the forward transform then the inverse.  Results
+ * are bit-identical across the three modes.  Plans must outlive the batches that use
+ * them; the data arrays must stay valid and may not overlap between jobs. */
+enum { NTT_OP_FORWARD = 1, NTT_OP_INVERSE = 2, NTT_OP_FORWARD_INVERSE = 3 };
+enum { NTT_BATCH_PLAIN = 0, NTT_BATCH_GROUPED = 1, NTT_BATCH_GRAPH = 2 };
+
+typedef struct {
+    ntt_plan_t plan;
+    uint64_t* d_data;     /* [n_polys][n_limbs][N] uint64, device, 16-byte aligned    */
+    uint32_t n_polys;     /* >= 1                                                     */
+    uint32_t n_limbs;     /* 1..L: the plan's first n_limbs primes; 0 = all L          */
+    uint32_t op;          /* NTT_OP_*                                                 */
+    uint32_t reserved;    /* must be zero                                             */
+} ntt_job;
+
+typedef struct ntt_batch_s* ntt_batch_t;
+
+/* Validate `n_jobs` jobs (copied; the array may be freed afterwards) and upload their
+ * vector descriptors to the device of the first job's plan.  Errors: NTT_ERR_ARG for a
+ * null plan or buffer, a bad op, n_limbs above L, mixed devices; NTT_ERR_NOMEM; NTT_ERR_HIP. */
+ntt_status ntt_batch_create(ntt_batch_t* out, const ntt_job* jobs, uint32_t n_jobs);
+
+/* Enqueue one run of the batch on `stream` in the given NTT_BATCH_* mode. */
+ntt_status ntt_batch_run(ntt_batch_t batch, int32_t mode, void* stream);
+
+/* Release the batch (its descriptors, private stream and captured graph).  The caller
+ * must make sure no run is still in flight.  NULL is accepted. */
+ntt_status ntt_batch_destroy(ntt_batch_t batch);
+
 /* Human-readable name of a status code (static storage). */
 const char* ntt_status_string(ntt_status s);
 

@@ -18,14 +18,19 @@ __all__ = [
     "NttError", "Plan", "ntt_plan_create", "ntt_plan_destroy", "ntt_plan_get_roots", "ntt_plan_get_info",
     "ntt_forward", "ntt_inverse", "ntt_forward_pass", "ntt_inverse_pass", "ntt_plan_num_passes",
     "ntt_pointwise_mul", "ntt_polymul_negacyclic", "ntt_status_string",
+    "Batch", "ntt_batch_create", "ntt_batch_run", "ntt_batch_destroy", "OP_FORWARD", "OP_INVERSE",
+    "OP_FORWARD_INVERSE", "BATCH_PLAIN", "BATCH_GROUPED", "BATCH_GRAPH",
     "library_path", "TWIDDLE_AUTO", "TWIDDLE_TABLE", "TWIDDLE_OT", "PATH_AUTO", "PATH_SPLIT", "PATH_FUSED",
 ]
 
 TWIDDLE_AUTO, TWIDDLE_TABLE, TWIDDLE_OT = 0, 1, 2
 PATH_AUTO, PATH_SPLIT, PATH_FUSED = 0, 1, 2
+OP_FORWARD, OP_INVERSE, OP_FORWARD_INVERSE = 1, 2, 3
+BATCH_PLAIN, BATCH_GROUPED, BATCH_GRAPH = 0, 1, 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libntt_mi355x.so")
+# NTT_MI355X_LIB selects another build of the library (e.g. a tuning variant).
+_LIB_PATH = os.environ.get("NTT_MI355X_LIB") or os.path.join(_HERE, "libntt_mi355x.so")
 
 
 def library_path() -> str:
@@ -46,6 +51,13 @@ class _Opts(ctypes.Structure):
 
 _vp = ctypes.c_void_p
 _u32 = ctypes.c_uint32
+
+
+class _Job(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("d_data", ctypes.c_void_p), ("n_polys", ctypes.c_uint32),
+                ("n_limbs", ctypes.c_uint32), ("op", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 _lib.ntt_plan_create.argtypes = [ctypes.POINTER(_vp), _u32, _u64p, _u32, ctypes.POINTER(_Opts)]
 _lib.ntt_plan_destroy.argtypes = [_vp]
@@ -61,12 +73,16 @@ _lib.ntt_plan_num_passes.argtypes = [_vp]
 _lib.ntt_plan_num_passes.restype = _u32
 _lib.ntt_pointwise_mul.argtypes = [_vp, _vp, _vp, _vp, _u32, _vp]
 _lib.ntt_polymul_negacyclic.argtypes = [_vp, _vp, _vp, _vp, _u32, _vp]
+_lib.ntt_batch_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_Job), _u32]
+_lib.ntt_batch_run.argtypes = [_vp, ctypes.c_int32, _vp]
+_lib.ntt_batch_destroy.argtypes = [_vp]
 _lib.ntt_status_string.argtypes = [ctypes.c_int]
 _lib.ntt_status_string.restype = ctypes.c_char_p
 _lib.ntt_last_error.argtypes = []
 _lib.ntt_last_error.restype = ctypes.c_char_p
 for _f in ("ntt_plan_create", "ntt_plan_destroy", "ntt_plan_get_roots", "ntt_plan_get_info", "ntt_forward",
-           "ntt_inverse", "ntt_forward_pass", "ntt_inverse_pass", "ntt_pointwise_mul", "ntt_polymul_negacyclic"):
+           "ntt_inverse", "ntt_forward_pass", "ntt_inverse_pass", "ntt_pointwise_mul", "ntt_polymul_negacyclic",
+           "ntt_batch_create", "ntt_batch_run", "ntt_batch_destroy"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -192,3 +208,47 @@ def ntt_pointwise_mul(plan: Plan, a, b, c, n_polys: int | None = None, stream=No
 def ntt_polymul_negacyclic(plan: Plan, a, b, c, n_polys: int | None = None, stream=None) -> None:
     _check(_lib.ntt_polymul_negacyclic(plan.handle, _addr(a), _addr(b), _addr(c), _polys(plan, a, n_polys),
                                        _stream(stream)), "ntt_polymul_negacyclic")
+
+
+class Batch:
+    """Owns an ntt_batch_t.  Keeps the plans (and buffers passed as tensors) of its jobs alive."""
+
+    def __init__(self, handle: int, keep):
+        self.handle = handle
+        self._keep = keep
+
+    def destroy(self) -> None:
+        if self.handle:
+            _check(_lib.ntt_batch_destroy(self.handle), "ntt_batch_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def ntt_batch_create(jobs) -> Batch:
+    """jobs: iterable of (plan, data, n_polys, n_limbs, op); n_polys None = from data's size,
+    n_limbs 0 = all of the plan's primes."""
+    jobs = list(jobs)
+    arr = (_Job * len(jobs))()
+    keep = []
+    for i, (plan, data, n_polys, n_limbs, op) in enumerate(jobs):
+        limbs = n_limbs or plan.L
+        if n_polys is None:
+            n_polys = data.numel() // (plan.N * limbs)
+        arr[i] = _Job(plan.handle, _addr(data), int(n_polys), int(n_limbs), int(op), 0)
+        keep.append((plan, data))
+    h = _vp()
+    _check(_lib.ntt_batch_create(ctypes.byref(h), arr, len(jobs)), "ntt_batch_create")
+    return Batch(h.value, keep)
+
+
+def ntt_batch_run(batch: Batch, mode: int = BATCH_GRAPH, stream=None) -> None:
+    _check(_lib.ntt_batch_run(batch.handle, int(mode), _stream(stream)), "ntt_batch_run")
+
+
+def ntt_batch_destroy(batch: Batch) -> None:
+    batch.destroy()

@@ -14,8 +14,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-BUILD = os.path.join(ROOT, "_build", "ntt")
-LIB = os.path.join(HERE, "libntt_mi355x.so")
+BUILD = os.environ.get("NTT_BUILD_DIR") or os.path.join(ROOT, "_build", "ntt")
+LIB = os.environ.get("NTT_BUILD_OUT") or os.path.join(HERE, "libntt_mi355x.so")
 SOURCES = ["kernels_fwd_fast.hip", "kernels_inv_fast.hip", "kernels_fwd_wide.hip", "kernels_inv_wide.hip",
            "fused_fwd.hip", "fused_inv.hip", "kernels.hip", "capi.cpp"]
 ARCH = os.environ.get("NTT_OFFLOAD_ARCH", "gfx950")
@@ -26,7 +26,7 @@ FLAGS = [
     # packed-FP32 instructions are disabled for every HIP translation unit
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-]
+] + os.environ.get("NTT_EXTRA_FLAGS", "").split()
 
 
 def _compile(src: str) -> str:

@@ -112,16 +112,19 @@ struct ntt_plan_s {
       if (p) (void)hipFree(p);
   }
 
-  PassArgs args(uint64_t* data, uint32_t n_polys, bool inverse) const {
+  PassArgs args(uint64_t* data, uint32_t n_polys, bool inverse, uint32_t limbs = 0) const {
     PassArgs a{};
     a.data = data;
+    a.vecs = nullptr;
     a.tw = inverse ? d_tw_inv : d_tw_fwd;
     a.ot_lo = inverse ? d_ot_lo_inv : d_ot_lo_fwd;
     a.ot_hi = inverse ? d_ot_hi_inv : d_ot_hi_fwd;
     a.q = d_q;
     a.scale = d_scale;
-    a.n_vec = (uint64_t)n_polys * L;
-    a.L = L;
+    const uint32_t Lu = limbs ? limbs : L;
+    a.n_vec = (uint64_t)n_polys * Lu;
+    a.P = n_polys;
+    a.L = Lu;
     a.logN = logN;
     a.logN1 = logN1;
     a.ot_log2_base = ot_log2_base;
@@ -302,9 +305,10 @@ static hipError_t launch_fused(ntt_plan_t plan, uint64_t* data, uint32_t n_polys
   return hipSuccess;
 }
 
-static hipError_t transform(ntt_plan_t plan, uint64_t* data, uint32_t n_polys, bool inverse, hipStream_t st) {
-  if (plan->fused_for(n_polys)) return launch_fused(plan, data, n_polys, inverse, st);
-  const PassArgs a = plan->args(data, n_polys, inverse);
+static hipError_t transform(ntt_plan_t plan, uint64_t* data, uint32_t n_polys, bool inverse, hipStream_t st,
+                            uint32_t limbs = 0) {
+  if ((limbs == 0 || limbs == plan->L) && plan->fused_for(n_polys)) return launch_fused(plan, data, n_polys, inverse, st);
+  const PassArgs a = plan->args(data, n_polys, inverse, limbs);
   return inverse ? nttk::launch_inverse(a, plan->active_ot(), st) : nttk::launch_forward(a, plan->active_ot(), st);
 }
 
@@ -316,6 +320,101 @@ static ntt_status check_data(ntt_plan_t plan, const void* ptr, uint32_t n_polys)
   // every pass launches at most N/16 + 1 workgroups per vector; keep the grid below 2^31
   const uint64_t n_vec = (uint64_t)n_polys * plan->L;
   if (n_vec * ((uint64_t)plan->N / 16 + 1) >= (1ull << 31)) return fail(NTT_ERR_ARG, "batch too large for one launch");
+  return NTT_OK;
+}
+
+// ---------------------------------------------------------------- batches
+
+struct ntt_batch_s {
+  struct Group {                        // every vector of the jobs that share one plan
+    ntt_plan_t plan = nullptr;
+    nttk::VecDesc* d_fwd = nullptr;     // vectors that run the forward transform
+    nttk::VecDesc* d_inv = nullptr;     // vectors that run the inverse transform
+    uint64_t n_fwd = 0, n_inv = 0;
+  };
+  std::vector<ntt_job> jobs;
+  std::vector<Group> groups;
+  int device = 0;
+  hipStream_t capture_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+
+  ~ntt_batch_s() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    for (auto& g : groups) {
+      if (g.d_fwd) (void)hipFree(g.d_fwd);
+      if (g.d_inv) (void)hipFree(g.d_inv);
+    }
+  }
+
+  // Enqueue the grouped work: all forward vector lists, then all inverse lists.
+  hipError_t grouped(hipStream_t st) const {
+    for (int phase = 0; phase < 2; ++phase) {
+      for (const Group& g : groups) {
+        const uint64_t n = phase ? g.n_inv : g.n_fwd;
+        if (!n) continue;
+        PassArgs a = g.plan->args(nullptr, 1, phase == 1);
+        a.vecs = phase ? g.d_inv : g.d_fwd;
+        a.n_vec = n;
+        a.P = 1;
+        a.L = g.plan->L;
+        const hipError_t e = phase ? nttk::launch_inverse(a, g.plan->active_ot(), st)
+                                   : nttk::launch_forward(a, g.plan->active_ot(), st);
+        if (e != hipSuccess) return e;
+      }
+    }
+    return hipSuccess;
+  }
+};
+
+static ntt_status build_batch(ntt_batch_s* b, const ntt_job* jobs, uint32_t n_jobs) {
+  b->jobs.assign(jobs, jobs + n_jobs);
+  std::vector<ntt_plan_t> plans;
+  for (uint32_t j = 0; j < n_jobs; ++j) {
+    const ntt_job& job = b->jobs[j];
+    if (!job.plan || !job.d_data) return fail(NTT_ERR_ARG, "job " + std::to_string(j) + ": NULL plan or data");
+    if (reinterpret_cast<uintptr_t>(job.d_data) & 15) return fail(NTT_ERR_ARG, "job data must be 16-byte aligned");
+    if (job.n_polys == 0 || job.n_limbs > job.plan->L || job.reserved)
+      return fail(NTT_ERR_ARG, "job " + std::to_string(j) + ": bad n_polys, n_limbs or reserved field");
+    if (job.op < NTT_OP_FORWARD || job.op > NTT_OP_FORWARD_INVERSE)
+      return fail(NTT_ERR_ARG, "job " + std::to_string(j) + ": bad op");
+    if (job.plan->device != b->jobs[0].plan->device) return fail(NTT_ERR_ARG, "jobs span several devices");
+    if (std::find(plans.begin(), plans.end(), job.plan) == plans.end()) plans.push_back(job.plan);
+  }
+  b->device = b->jobs[0].plan->device;
+  hipError_t e;
+  for (ntt_plan_t plan : plans) {
+    ntt_batch_s::Group g;
+    g.plan = plan;
+    std::vector<nttk::VecDesc> fwd, inv;
+    // limb-major: the polynomials of one limb are adjacent, so launches meet its twiddles together
+    for (uint32_t l = 0; l < plan->L; ++l) {
+      for (const ntt_job& job : b->jobs) {
+        if (job.plan != plan) continue;
+        const uint32_t lim = job.n_limbs ? job.n_limbs : plan->L;
+        if (l >= lim) continue;
+        for (uint32_t p = 0; p < job.n_polys; ++p) {
+          const nttk::VecDesc d{job.d_data + ((uint64_t)p * lim + l) * plan->N, l, 0};
+          if (job.op & NTT_OP_FORWARD) fwd.push_back(d);
+          if (job.op & NTT_OP_INVERSE) inv.push_back(d);
+        }
+      }
+    }
+    for (auto* list : {&fwd, &inv}) {
+      if (list->size() * ((uint64_t)plan->N / 16 + 1) >= (1ull << 31))
+        return fail(NTT_ERR_ARG, "batch too large for one launch");
+    }
+    if ((e = upload(&g.d_fwd, fwd)) != hipSuccess || (e = upload(&g.d_inv, inv)) != hipSuccess) {
+      b->groups.push_back(g);
+      return e == hipErrorOutOfMemory ? fail(NTT_ERR_NOMEM, "descriptor allocation failed")
+                                      : hip_fail(e, "uploading batch descriptors");
+    }
+    g.n_fwd = fwd.size();
+    g.n_inv = inv.size();
+    b->groups.push_back(g);
+  }
   return NTT_OK;
 }
 
@@ -499,6 +598,80 @@ ntt_status ntt_polymul_negacyclic(ntt_plan_t plan, const uint64_t* d_a, const ui
     return NTT_OK;
   } catch (...) {
     return fail(NTT_ERR_ARG, "unexpected failure in ntt_polymul_negacyclic");
+  }
+}
+
+ntt_status ntt_batch_create(ntt_batch_t* out, const ntt_job* jobs, uint32_t n_jobs) {
+  try {
+    if (!out) return fail(NTT_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!jobs || n_jobs == 0) return fail(NTT_ERR_ARG, "jobs must be a non-empty array");
+    if (!jobs[0].plan) return fail(NTT_ERR_ARG, "job 0: NULL plan");
+    DeviceGuard g(jobs[0].plan->device);
+    if (!g.ok) return fail(NTT_ERR_HIP, "cannot select the plans' device");
+    ntt_batch_s* b = new (std::nothrow) ntt_batch_s();
+    if (!b) return fail(NTT_ERR_NOMEM, "host allocation failed");
+    const ntt_status s = build_batch(b, jobs, n_jobs);
+    if (s != NTT_OK) {
+      delete b;
+      return s;
+    }
+    *out = b;
+    return NTT_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(NTT_ERR_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(NTT_ERR_ARG, "unexpected failure in ntt_batch_create");
+  }
+}
+
+ntt_status ntt_batch_run(ntt_batch_t b, int32_t mode, void* stream) {
+  try {
+    if (!b) return fail(NTT_ERR_ARG, "batch is NULL");
+    DeviceGuard g(b->device);
+    if (!g.ok) return fail(NTT_ERR_HIP, "cannot select the batch's device");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    if (mode == NTT_BATCH_PLAIN) {
+      for (const ntt_job& job : b->jobs) {
+        if ((job.op & NTT_OP_FORWARD) && (e = transform(job.plan, job.d_data, job.n_polys, false, st, job.n_limbs)))
+          break;
+        if ((job.op & NTT_OP_INVERSE) && (e = transform(job.plan, job.d_data, job.n_polys, true, st, job.n_limbs)))
+          break;
+      }
+    } else if (mode == NTT_BATCH_GROUPED) {
+      e = b->grouped(st);
+    } else if (mode == NTT_BATCH_GRAPH) {
+      if (!b->exec) {
+        if ((e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking)) != hipSuccess)
+          return hip_fail(e, "creating the capture stream");
+        if ((e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+          return hip_fail(e, "hipStreamBeginCapture");
+        const hipError_t le = b->grouped(b->capture_stream);
+        e = hipStreamEndCapture(b->capture_stream, &b->graph);
+        if (le != hipSuccess) return hip_fail(le, "capturing the batch");
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess)
+          return hip_fail(e, "hipGraphInstantiate");
+      }
+      e = hipGraphLaunch(b->exec, st);
+    } else {
+      return fail(NTT_ERR_ARG, "unknown batch mode");
+    }
+    return e == hipSuccess ? NTT_OK : hip_fail(e, "ntt_batch_run");
+  } catch (...) {
+    return fail(NTT_ERR_ARG, "unexpected failure in ntt_batch_run");
+  }
+}
+
+ntt_status ntt_batch_destroy(ntt_batch_t b) {
+  try {
+    if (!b) return NTT_OK;
+    DeviceGuard g(b->device);
+    delete b;
+    return NTT_OK;
+  } catch (...) {
+    return fail(NTT_ERR_ARG, "unexpected failure in ntt_batch_destroy");
   }
 }
 

@@ -42,7 +42,7 @@ struct FusedShape {
   static constexpr int M1 = 1 << LOGM1;      // column length N1
   static constexpr int C = 4096 / M1;        // columns per column tile
   static constexpr int TC = M1 / SC::R;      // lanes per column
-  using RC = RowCfg<LOGM2>;                  // row tile: V rows of M2
+  using RC = RowCfg<LOGM2, (int)kFusedThreads>;   // row tile: V rows of M2
   static constexpr int M2 = 1 << LOGM2;
   static constexpr int Tc = M2 / C;          // column tiles per vector
   static constexpr int Tr = M1 / RC::V;      // row tiles per vector

@@ -8,16 +8,39 @@
 namespace nttk {
 
 constexpr int kLR = 4;          // 16 values per lane per register step
-constexpr int kColWidth = 16;   // columns per column-pass workgroup: 16 x 8 B = one 128 B line
+#ifndef NTTK_COL_WIDTH
+#define NTTK_COL_WIDTH 8
+#endif
+#ifndef NTTK_ROW_THREADS
+#define NTTK_ROW_THREADS 128
+#endif
+constexpr int kColWidth = NTTK_COL_WIDTH;     // columns per column-pass tile
+constexpr int kRowThreads = NTTK_ROW_THREADS; // lanes per row-pass workgroup
+
+// Tile of this workgroup.  Workgroups are dispatched to the eight XCDs round-robin (block
+// b runs on XCD b mod 8), so XCD x gets the contiguous tile range [x*per, (x+1)*per):
+// neighbouring tiles, which share cache lines (column tiles) or twiddles (row tiles of
+// the polynomials of one limb), then meet in one L2.  The grid is 8*per workgroups;
+// tiles past the end are padding.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t n_tiles) {
+  const uint32_t per = (n_tiles + 7) / 8;
+  return (blockIdx.x % 8) * per + blockIdx.x / 8;
+}
+
+// Limb-major order of the vectors of a [P][L] batch: position lp = l*P + p holds vector
+// p*L + l, so the polynomials of one limb (one prime, one twiddle table) are adjacent.
+__device__ __forceinline__ uint64_t limb_major_vec(uint64_t lp, uint32_t L, uint32_t P) {
+  return (lp % P) * L + lp / P;
+}
 
 __device__ __forceinline__ uint32_t lds_pad(uint32_t r) { return r + (r >> 4); }
 
-template <int LOGM>
+template <int LOGM, int NTH = kRowThreads>
 struct RowCfg {
   using S = Steps<LOGM, kLR>;
   static constexpr int M = 1 << LOGM;
   static constexpr int T = M / S::R;                    // lanes per row
-  static constexpr int V = T >= 256 ? 1 : 256 / T;      // rows per workgroup
+  static constexpr int V = T >= NTH ? 1 : NTH / T;      // rows per workgroup
   static constexpr int NT = V * T;
   static constexpr int PITCH = M >= 16 ? M + M / 16 : M;
 };
@@ -34,11 +57,18 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void fwd_row_kernel(PassArgs a) {
   __shared__ uint64_t lds[C::V * C::PITCH];
   const uint32_t tid = threadIdx.x, v = tid / C::T, t = tid % C::T;
   const uint64_t rows = a.n_vec << a.logN1;
-  const uint64_t g0 = (uint64_t)blockIdx.x * C::V + v;
-  const bool valid = g0 < rows;
-  const uint64_t g = valid ? g0 : 0;
+  const uint32_t n_tiles = (uint32_t)((rows + C::V - 1) / C::V);
+  const uint32_t tile = xcd_tile(n_tiles);
+  const uint64_t h0 = (uint64_t)tile * C::V + v;   // row in limb-major order (natural when N1 = 1)
+  const bool valid = tile < n_tiles && h0 < rows;
   const uint32_t N1 = 1u << a.logN1;
-  const uint32_t limb = (uint32_t)((g >> a.logN1) % a.L);
+  uint64_t g = 0;   // row index in [vector][row] order
+  if (valid) {
+    const uint64_t lp = h0 >> a.logN1;
+    g = ((a.vecs || !a.logN1 ? lp : limb_major_vec(lp, a.L, a.P)) << a.logN1) | (h0 & (N1 - 1));
+  }
+  const VecRef vr = vec_ref(a, g >> a.logN1);
+  const uint32_t limb = vr.limb;
   const Mod md(a.q[limb]);
   const uint32_t base = N1 + (uint32_t)(g & (N1 - 1));
   const Tw* tab = a.tw + ((size_t)limb << a.logN);
@@ -50,7 +80,7 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void fwd_row_kernel(PassArgs a) {
     ot.b = a.ot_log2_base;
   }
   auto tabfn = [&](uint32_t ix) { return tab[ix]; };
-  uint64_t* rowp = a.data + g * C::M;
+  uint64_t* rowp = vr.base + (g & (N1 - 1)) * C::M;
   uint64_t* l = lds + v * C::PITCH;
 
   uint64_t x[S::R];
@@ -94,11 +124,18 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void inv_row_kernel(PassArgs a) {
   __shared__ uint64_t lds[C::V * C::PITCH];
   const uint32_t tid = threadIdx.x, v = tid / C::T, t = tid % C::T;
   const uint64_t rows = a.n_vec << a.logN1;
-  const uint64_t g0 = (uint64_t)blockIdx.x * C::V + v;
-  const bool valid = g0 < rows;
-  const uint64_t g = valid ? g0 : 0;
+  const uint32_t n_tiles = (uint32_t)((rows + C::V - 1) / C::V);
+  const uint32_t tile = xcd_tile(n_tiles);
+  const uint64_t h0 = (uint64_t)tile * C::V + v;   // row in limb-major order (natural when N1 = 1)
+  const bool valid = tile < n_tiles && h0 < rows;
   const uint32_t N1 = 1u << a.logN1;
-  const uint32_t limb = (uint32_t)((g >> a.logN1) % a.L);
+  uint64_t g = 0;   // row index in [vector][row] order
+  if (valid) {
+    const uint64_t lp = h0 >> a.logN1;
+    g = ((a.vecs || !a.logN1 ? lp : limb_major_vec(lp, a.L, a.P)) << a.logN1) | (h0 & (N1 - 1));
+  }
+  const VecRef vr = vec_ref(a, g >> a.logN1);
+  const uint32_t limb = vr.limb;
   const Mod md(a.q[limb]);
   const uint32_t base = N1 + (uint32_t)(g & (N1 - 1));
   const Tw* tab = a.tw + ((size_t)limb << a.logN);
@@ -115,7 +152,7 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void inv_row_kernel(PassArgs a) {
     sc1 = a.scale[2 * limb + 1];
   }
   auto tabfn = [&](uint32_t ix) { return tab[ix]; };
-  uint64_t* rowp = a.data + g * C::M;
+  uint64_t* rowp = vr.base + (g & (N1 - 1)) * C::M;
   uint64_t* l = lds + v * C::PITCH;
 
   uint64_t x[S::R];
@@ -175,13 +212,17 @@ __global__ __launch_bounds__(ColCfg<LOGM>::NT) void fwd_col_kernel(PassArgs a) {
   const uint32_t tid = threadIdx.x, c = tid % C::W, t = tid / C::W;
   const uint32_t logN2 = a.logN - LOGM;
   const uint32_t groups = (1u << logN2) / C::W;
-  const uint64_t vec = blockIdx.x / groups;
-  const uint32_t cg = blockIdx.x % groups;
-  const uint32_t limb = (uint32_t)(vec % a.L);
+  const uint32_t n_tiles = (uint32_t)(a.n_vec * groups);
+  const uint32_t tile = xcd_tile(n_tiles);
+  if (tile >= n_tiles) return;   // padding workgroup (uniform: no barrier is skipped by part of it)
+  const uint64_t vec = a.vecs ? tile / groups : limb_major_vec(tile / groups, a.L, a.P);
+  const uint32_t cg = tile % groups;
+  const VecRef vr = vec_ref(a, vec);
+  const uint32_t limb = vr.limb;
   const Mod md(a.q[limb]);
   const Tw* tab = a.tw + ((size_t)limb << a.logN);
   for (uint32_t i = tid; i < (uint32_t)C::M; i += C::NT) twl[i] = tab[i];
-  uint64_t* colp = a.data + (vec << a.logN) + cg * C::W + c;
+  uint64_t* colp = vr.base + cg * C::W + c;
 
   uint64_t x[S::R];
 #pragma unroll
@@ -216,14 +257,18 @@ __global__ __launch_bounds__(ColCfg<LOGM>::NT) void inv_col_kernel(PassArgs a) {
   const uint32_t tid = threadIdx.x, c = tid % C::W, t = tid / C::W;
   const uint32_t logN2 = a.logN - LOGM;
   const uint32_t groups = (1u << logN2) / C::W;
-  const uint64_t vec = blockIdx.x / groups;
-  const uint32_t cg = blockIdx.x % groups;
-  const uint32_t limb = (uint32_t)(vec % a.L);
+  const uint32_t n_tiles = (uint32_t)(a.n_vec * groups);
+  const uint32_t tile = xcd_tile(n_tiles);
+  if (tile >= n_tiles) return;   // padding workgroup (uniform: no barrier is skipped by part of it)
+  const uint64_t vec = a.vecs ? tile / groups : limb_major_vec(tile / groups, a.L, a.P);
+  const uint32_t cg = tile % groups;
+  const VecRef vr = vec_ref(a, vec);
+  const uint32_t limb = vr.limb;
   const Mod md(a.q[limb]);
   const Tw* tab = a.tw + ((size_t)limb << a.logN);
   for (uint32_t i = tid; i < (uint32_t)C::M; i += C::NT) twl[i] = tab[i];
   const Tw sc0 = a.scale[2 * limb], sc1 = a.scale[2 * limb + 1];
-  uint64_t* colp = a.data + (vec << a.logN) + cg * C::W + c;
+  uint64_t* colp = vr.base + cg * C::W + c;
 
   uint64_t x[S::R];
 #pragma unroll
@@ -254,7 +299,7 @@ template <bool FAST, int LOGM, int OTS>
 hipError_t go_fwd_row(const PassArgs& a, hipStream_t st) {
   using C = RowCfg<LOGM>;
   const uint64_t rows = a.n_vec << a.logN1;
-  const uint64_t blocks = (rows + C::V - 1) / C::V;
+  const uint64_t blocks = ((rows + C::V - 1) / C::V + 7) / 8 * 8;
   hipLaunchKernelGGL((fwd_row_kernel<FAST, LOGM, OTS>), dim3((uint32_t)blocks), dim3(C::NT), 0, st, a);
   return hipGetLastError();
 }
@@ -263,7 +308,7 @@ template <bool FAST, int LOGM, int OTS, bool SCALE0>
 hipError_t go_inv_row(const PassArgs& a, hipStream_t st) {
   using C = RowCfg<LOGM>;
   const uint64_t rows = a.n_vec << a.logN1;
-  const uint64_t blocks = (rows + C::V - 1) / C::V;
+  const uint64_t blocks = ((rows + C::V - 1) / C::V + 7) / 8 * 8;
   hipLaunchKernelGGL((inv_row_kernel<FAST, LOGM, OTS, SCALE0>), dim3((uint32_t)blocks), dim3(C::NT), 0, st, a);
   return hipGetLastError();
 }
@@ -271,7 +316,7 @@ hipError_t go_inv_row(const PassArgs& a, hipStream_t st) {
 template <bool FAST, int LOGM>
 hipError_t go_fwd_col(const PassArgs& a, hipStream_t st) {
   using C = ColCfg<LOGM>;
-  const uint64_t blocks = a.n_vec * ((1u << (a.logN - LOGM)) / C::W);
+  const uint64_t blocks = (a.n_vec * ((1u << (a.logN - LOGM)) / C::W) + 7) / 8 * 8;
   hipLaunchKernelGGL((fwd_col_kernel<FAST, LOGM>), dim3((uint32_t)blocks), dim3(C::NT), 0, st, a);
   return hipGetLastError();
 }
@@ -279,7 +324,7 @@ hipError_t go_fwd_col(const PassArgs& a, hipStream_t st) {
 template <bool FAST, int LOGM>
 hipError_t go_inv_col(const PassArgs& a, hipStream_t st) {
   using C = ColCfg<LOGM>;
-  const uint64_t blocks = a.n_vec * ((1u << (a.logN - LOGM)) / C::W);
+  const uint64_t blocks = (a.n_vec * ((1u << (a.logN - LOGM)) / C::W) + 7) / 8 * 8;
   hipLaunchKernelGGL((inv_col_kernel<FAST, LOGM>), dim3((uint32_t)blocks), dim3(C::NT), 0, st, a);
   return hipGetLastError();
 }

@@ -22,20 +22,44 @@
 
 namespace nttk {
 
+// One limb-vector of a vector-list launch: its residues and the plan limb (prime) it uses.
+struct VecDesc {
+  uint64_t* ptr;
+  uint32_t limb;
+  uint32_t pad;
+};
+
 struct PassArgs {
-  uint64_t* data;        // batch base, [n_vec][N]
+  uint64_t* data;        // batch base, [n_vec][N] (dense launches)
+  const VecDesc* vecs;   // vector list (list launches) or null
   const Tw* tw;          // [L][N] twiddles of this direction (Psi or Psi_inv)
   const Tw* ot_lo;       // [L][B]     psi^{+-k},     k < B       (OT only)
   const Tw* ot_hi;       // [L][N/B]   psi^{+-B*h},   h < N/B     (OT only)
   const uint64_t* q;     // [L]
   const Tw* scale;       // [L][2]: {1/N}, {Psi_inv[1]/N}        (inverse only)
   uint64_t n_vec;        // vectors in the batch (n_polys * L)
+  uint32_t P;            // polynomials in the batch
   uint32_t L;
   uint32_t logN;
   uint32_t logN1;        // log2 of the column-pass size (0: single pass)
   uint32_t ot_log2_base; // log2 B
   uint32_t fast;         // every prime below 2^60: the Arith<true> policy applies
 };
+
+// Base address and limb of vector `vec` of a launch: dense [P][L][N] batches place vector
+// p*L + l at data + (p*L + l)*N with prime l; list launches read both from the list.
+struct VecRef {
+  uint64_t* base;
+  uint32_t limb;
+};
+
+__device__ __forceinline__ VecRef vec_ref(const PassArgs& a, uint64_t vec) {
+  if (a.vecs) {
+    const VecDesc d = a.vecs[vec];
+    return VecRef{d.ptr, d.limb};
+  }
+  return VecRef{a.data + (vec << a.logN), (uint32_t)(vec % a.L)};
+}
 
 template <int Begin, int End, typename F>
 __device__ __forceinline__ void static_for(F&& f) {

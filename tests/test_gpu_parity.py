@@ -299,3 +299,51 @@ def test_plan_reuse_across_streams():
         assert np.array_equal(host(d1), want) and np.array_equal(host(d2), want)
     finally:
         plan.destroy()
+
+
+# ------------------------------------------------------------------ batches of uneven jobs
+
+@pytest.mark.parametrize("mode", ["plain", "grouped", "graph"])
+def test_batch_uneven_jobs(mode):
+    """Jobs of several N and limb counts (prefixes of one prime chain), mixed ops, in one
+    batch; every job is checked against the oracle and the three run modes agree."""
+    n_max = 1 << 16
+    chain = synth.gen_primes(1000, n_max, 60, 6)
+    plans = {logN: ntt.ntt_plan_create(1 << logN, chain) for logN in (4, 10, 13, 16)}
+    spec = [(4, 1, 2, ntt.OP_FORWARD), (10, 3, 1, ntt.OP_FORWARD_INVERSE), (13, 6, 2, ntt.OP_INVERSE),
+            (16, 2, 1, ntt.OP_FORWARD), (16, 5, 2, ntt.OP_FORWARD_INVERSE), (10, 6, 3, ntt.OP_INVERSE),
+            (13, 1, 1, ntt.OP_FORWARD), (4, 6, 1, ntt.OP_FORWARD_INVERSE)]
+    try:
+        jobs, bufs, want = [], [], []
+        for k, (logN, limbs, polys, op) in enumerate(spec):
+            N = 1 << logN
+            primes = chain[:limbs]
+            data = synth.residue_batch(1100 + k, primes, N, polys)
+            psis = oracle.roots(primes, N)
+            if op == ntt.OP_FORWARD:
+                w = oracle.forward(data, primes, psis, THREADS)
+            elif op == ntt.OP_INVERSE:
+                w = oracle.inverse(data, primes, psis, THREADS)
+            else:
+                w = data.copy()
+            d = dev(data)
+            bufs.append(d)
+            want.append(w)
+            jobs.append((plans[logN], d, polys, limbs if limbs < len(chain) else 0, op))
+        batch = ntt.ntt_batch_create(jobs)
+        m = {"plain": ntt.BATCH_PLAIN, "grouped": ntt.BATCH_GROUPED, "graph": ntt.BATCH_GRAPH}[mode]
+        ntt.ntt_batch_run(batch, m)
+        torch.cuda.synchronize()
+        for d, w in zip(bufs, want):
+            assert np.array_equal(host(d), w)
+        if mode == "graph":   # replays: forward-only jobs advance, round-trip jobs stay put
+            for _ in range(3):
+                ntt.ntt_batch_run(batch, m)
+                torch.cuda.synchronize()
+            for (logN, limbs, polys, op), d, w in zip(spec, bufs, want):
+                if op == ntt.OP_FORWARD_INVERSE:
+                    assert np.array_equal(host(d), w)
+        batch.destroy()
+    finally:
+        for p in plans.values():
+            p.destroy()
