@@ -156,16 +156,20 @@ ntt_status ntt_polymul_negacyclic(ntt_plan_t plan, const uint64_t* d_a, const ui
  * so one plan over a long prime chain serves every limb count.  A batch object validates
  * the jobs once and uploads per-vector descriptors; runs then enqueue the work:
  *
- *   NTT_BATCH_PLAIN    one ntt_forward / ntt_inverse call per job (the baseline);
+ *   NTT_BATCH_PLAIN    one call per step of each job (the baseline);
  *   NTT_BATCH_GROUPED  one launch per pass over every vector of every job sharing a plan
- *                      (vector-list launches: all forward work first, then all inverse work);
+ *                      (vector-list launches: all forward work, then all key products, then
+ *                      all inverse work);
  *   NTT_BATCH_GRAPH    the GROUPED launches captured once into a hipGraph (on a stream the
  *                      batch owns) and replayed on the caller's stream on every run.
  *
- * Jobs with NTT_OP_FORWARD_INVERSE run the forward transform then the inverse.  Results
+ * op is a set of steps run in the order forward, key product, inverse: NTT_OP_MULKEY
+ * multiplies every polynomial of the job element-wise by the job's key, a device array
+ * [n_limbs][N] already in the NTT domain (the ciphertext-times-plaintext step of
+ * Section III-A's polynomial product).  Results
  * are bit-identical across the three modes.  Plans must outlive the batches that use
  * them; the data arrays must stay valid and may not overlap between jobs. */
-enum { NTT_OP_FORWARD = 1, NTT_OP_INVERSE = 2, NTT_OP_FORWARD_INVERSE = 3 };
+enum { NTT_OP_FORWARD = 1, NTT_OP_INVERSE = 2, NTT_OP_FORWARD_INVERSE = 3, NTT_OP_MULKEY = 4 };
 enum { NTT_BATCH_PLAIN = 0, NTT_BATCH_GROUPED = 1, NTT_BATCH_GRAPH = 2 };
 
 typedef struct {
@@ -173,8 +177,9 @@ typedef struct {
     uint64_t* d_data;     /* [n_polys][n_limbs][N] uint64, device, 16-byte aligned    */
     uint32_t n_polys;     /* >= 1                                                     */
     uint32_t n_limbs;     /* 1..L: the plan's first n_limbs primes; 0 = all L          */
-    uint32_t op;          /* NTT_OP_*                                                 */
+    uint32_t op;          /* NTT_OP_* bits (nonzero)                                   */
     uint32_t reserved;    /* must be zero                                             */
+    const uint64_t* d_key;/* [n_limbs][N] key in the NTT domain when op has MULKEY      */
 } ntt_job;
 
 typedef struct ntt_batch_s* ntt_batch_t;
@@ -183,6 +188,17 @@ typedef struct ntt_batch_s* ntt_batch_t;
  * vector descriptors to the device of the first job's plan.  Errors: NTT_ERR_ARG for a
  * null plan or buffer, a bad op, n_limbs above L, mixed devices; NTT_ERR_NOMEM; NTT_ERR_HIP. */
 ntt_status ntt_batch_create(ntt_batch_t* out, const ntt_job* jobs, uint32_t n_jobs);
+
+/* Replace the jobs of an existing batch (same rules as ntt_batch_create; the plans must
+ * live on the batch's device).  The descriptors go through the batch's pinned staging
+ * buffer and are copied asynchronously on `stream`, which first waits for the batch's last
+ * run, into the batch's device storage; that storage grows only when the new job set needs
+ * more (growth blocks the host until the earlier work is done).  A captured graph is
+ * dropped and re-captured by the next NTT_BATCH_GRAPH run.  Runs of the batch must then be
+ * enqueued on `stream` (or ordered after it).  Meant for request loops that reuse a few
+ * batch objects instead of creating one per iteration.  On error the batch is left with
+ * no jobs (its runs enqueue nothing) until the next successful assign. */
+ntt_status ntt_batch_assign(ntt_batch_t batch, const ntt_job* jobs, uint32_t n_jobs, void* stream);
 
 /* Enqueue one run of the batch on `stream` in the given NTT_BATCH_* mode. */
 ntt_status ntt_batch_run(ntt_batch_t batch, int32_t mode, void* stream);

@@ -18,14 +18,14 @@ __all__ = [
     "NttError", "Plan", "ntt_plan_create", "ntt_plan_destroy", "ntt_plan_get_roots", "ntt_plan_get_info",
     "ntt_forward", "ntt_inverse", "ntt_forward_pass", "ntt_inverse_pass", "ntt_plan_num_passes",
     "ntt_pointwise_mul", "ntt_polymul_negacyclic", "ntt_status_string",
-    "Batch", "ntt_batch_create", "ntt_batch_run", "ntt_batch_destroy", "OP_FORWARD", "OP_INVERSE",
-    "OP_FORWARD_INVERSE", "BATCH_PLAIN", "BATCH_GROUPED", "BATCH_GRAPH",
+    "Batch", "ntt_batch_create", "ntt_batch_run", "ntt_batch_destroy", "ntt_batch_assign", "OP_FORWARD", "OP_INVERSE",
+    "OP_FORWARD_INVERSE", "OP_MULKEY", "BATCH_PLAIN", "BATCH_GROUPED", "BATCH_GRAPH",
     "library_path", "TWIDDLE_AUTO", "TWIDDLE_TABLE", "TWIDDLE_OT", "PATH_AUTO", "PATH_SPLIT", "PATH_FUSED",
 ]
 
 TWIDDLE_AUTO, TWIDDLE_TABLE, TWIDDLE_OT = 0, 1, 2
 PATH_AUTO, PATH_SPLIT, PATH_FUSED = 0, 1, 2
-OP_FORWARD, OP_INVERSE, OP_FORWARD_INVERSE = 1, 2, 3
+OP_FORWARD, OP_INVERSE, OP_FORWARD_INVERSE, OP_MULKEY = 1, 2, 3, 4
 BATCH_PLAIN, BATCH_GROUPED, BATCH_GRAPH = 0, 1, 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -55,7 +55,8 @@ _u32 = ctypes.c_uint32
 
 class _Job(ctypes.Structure):
     _fields_ = [("plan", ctypes.c_void_p), ("d_data", ctypes.c_void_p), ("n_polys", ctypes.c_uint32),
-                ("n_limbs", ctypes.c_uint32), ("op", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("n_limbs", ctypes.c_uint32), ("op", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("d_key", ctypes.c_void_p)]
 
 
 _u64p = ctypes.POINTER(ctypes.c_uint64)
@@ -75,6 +76,7 @@ _lib.ntt_pointwise_mul.argtypes = [_vp, _vp, _vp, _vp, _u32, _vp]
 _lib.ntt_polymul_negacyclic.argtypes = [_vp, _vp, _vp, _vp, _u32, _vp]
 _lib.ntt_batch_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_Job), _u32]
 _lib.ntt_batch_run.argtypes = [_vp, ctypes.c_int32, _vp]
+_lib.ntt_batch_assign.argtypes = [_vp, ctypes.POINTER(_Job), _u32, _vp]
 _lib.ntt_batch_destroy.argtypes = [_vp]
 _lib.ntt_status_string.argtypes = [ctypes.c_int]
 _lib.ntt_status_string.restype = ctypes.c_char_p
@@ -82,7 +84,7 @@ _lib.ntt_last_error.argtypes = []
 _lib.ntt_last_error.restype = ctypes.c_char_p
 for _f in ("ntt_plan_create", "ntt_plan_destroy", "ntt_plan_get_roots", "ntt_plan_get_info", "ntt_forward",
            "ntt_inverse", "ntt_forward_pass", "ntt_inverse_pass", "ntt_pointwise_mul", "ntt_polymul_negacyclic",
-           "ntt_batch_create", "ntt_batch_run", "ntt_batch_destroy"):
+           "ntt_batch_create", "ntt_batch_run", "ntt_batch_destroy", "ntt_batch_assign"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -229,20 +231,36 @@ class Batch:
             pass
 
 
-def ntt_batch_create(jobs) -> Batch:
-    """jobs: iterable of (plan, data, n_polys, n_limbs, op); n_polys None = from data's size,
-    n_limbs 0 = all of the plan's primes."""
+def _jobs_array(jobs):
     jobs = list(jobs)
     arr = (_Job * len(jobs))()
     keep = []
-    for i, (plan, data, n_polys, n_limbs, op) in enumerate(jobs):
+    for i, job in enumerate(jobs):
+        plan, data, n_polys, n_limbs, op = job[:5]
+        key = job[5] if len(job) > 5 else None
         limbs = n_limbs or plan.L
         if n_polys is None:
             n_polys = data.numel() // (plan.N * limbs)
-        arr[i] = _Job(plan.handle, _addr(data), int(n_polys), int(n_limbs), int(op), 0)
-        keep.append((plan, data))
+        arr[i] = _Job(plan.handle, _addr(data), int(n_polys), int(n_limbs), int(op), 0,
+                      _addr(key) if key is not None else None)
+        keep.append((plan, data, key))
+    return arr, keep
+
+
+def ntt_batch_assign(batch: "Batch", jobs, stream=None) -> None:
+    """Replace the jobs of `batch`; descriptors are uploaded on `stream` (runs must follow there)."""
+    arr, keep = _jobs_array(jobs)
+    _check(_lib.ntt_batch_assign(batch.handle, arr, len(keep), _stream(stream)), "ntt_batch_assign")
+    batch._keep = keep
+
+
+def ntt_batch_create(jobs) -> Batch:
+    """jobs: iterable of (plan, data, n_polys, n_limbs, op) or (plan, data, n_polys, n_limbs, op, key);
+    n_polys None = from data's size, n_limbs 0 = all of the plan's primes, key = the NTT-domain
+    [n_limbs][N] array multiplied in when op has OP_MULKEY."""
+    arr, keep = _jobs_array(jobs)
     h = _vp()
-    _check(_lib.ntt_batch_create(ctypes.byref(h), arr, len(jobs)), "ntt_batch_create")
+    _check(_lib.ntt_batch_create(ctypes.byref(h), arr, len(keep)), "ntt_batch_create")
     return Batch(h.value, keep)
 
 

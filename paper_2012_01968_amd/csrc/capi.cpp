@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -328,35 +329,59 @@ static ntt_status check_data(ntt_plan_t plan, const void* ptr, uint32_t n_polys)
 struct ntt_batch_s {
   struct Group {                        // every vector of the jobs that share one plan
     ntt_plan_t plan = nullptr;
-    nttk::VecDesc* d_fwd = nullptr;     // vectors that run the forward transform
-    nttk::VecDesc* d_inv = nullptr;     // vectors that run the inverse transform
-    uint64_t n_fwd = 0, n_inv = 0;
+    uint64_t off_fwd = 0, off_key = 0, off_inv = 0;   // positions in the descriptor arena
+    uint64_t n_fwd = 0, n_key = 0, n_inv = 0;
   };
   std::vector<ntt_job> jobs;
   std::vector<Group> groups;
   int device = 0;
+  nttk::VecDesc* d_desc = nullptr;      // descriptor arena (device)
+  nttk::VecDesc* h_desc = nullptr;      // pinned staging copy of the arena
+  uint64_t cap = 0;                     // capacity of both, in descriptors
+  hipEvent_t used = nullptr;            // last run that read the arena
+  hipEvent_t uploaded = nullptr;        // last copy out of the staging buffer
+  bool used_pending = false, upload_pending = false;
   hipStream_t capture_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 
-  ~ntt_batch_s() {
+  void drop_graph() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
-    if (capture_stream) (void)hipStreamDestroy(capture_stream);
-    for (auto& g : groups) {
-      if (g.d_fwd) (void)hipFree(g.d_fwd);
-      if (g.d_inv) (void)hipFree(g.d_inv);
-    }
+    exec = nullptr;
+    graph = nullptr;
   }
 
-  // Enqueue the grouped work: all forward vector lists, then all inverse lists.
+  ~ntt_batch_s() {
+    for (hipEvent_t ev : {used, uploaded}) {
+      if (!ev) continue;
+      (void)hipEventSynchronize(ev);
+      (void)hipEventDestroy(ev);
+    }
+    drop_graph();
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    if (d_desc) (void)hipFree(d_desc);
+    if (h_desc) (void)hipHostFree(h_desc);
+  }
+
+  const nttk::VecDesc* at(uint64_t off) const { return d_desc + off; }
+
+  // Enqueue the grouped work: all forward vector lists, then the key products, then all
+  // inverse lists.
   hipError_t grouped(hipStream_t st) const {
-    for (int phase = 0; phase < 2; ++phase) {
+    for (int phase = 0; phase < 3; ++phase) {
       for (const Group& g : groups) {
+        if (phase == 1) {
+          if (!g.n_key) continue;
+          const hipError_t e = nttk::launch_pointwise_list(at(g.off_key), g.n_key, g.plan->logN, g.plan->d_q,
+                                                           g.plan->d_mu, g.plan->d_bits, st);
+          if (e != hipSuccess) return e;
+          continue;
+        }
         const uint64_t n = phase ? g.n_inv : g.n_fwd;
         if (!n) continue;
-        PassArgs a = g.plan->args(nullptr, 1, phase == 1);
-        a.vecs = phase ? g.d_inv : g.d_fwd;
+        PassArgs a = g.plan->args(nullptr, 1, phase == 2);
+        a.vecs = at(phase ? g.off_inv : g.off_fwd);
         a.n_vec = n;
         a.P = 1;
         a.L = g.plan->L;
@@ -369,52 +394,96 @@ struct ntt_batch_s {
   }
 };
 
-static ntt_status build_batch(ntt_batch_s* b, const ntt_job* jobs, uint32_t n_jobs) {
-  b->jobs.assign(jobs, jobs + n_jobs);
+// Validate the jobs and fill the batch's groups and descriptors (host side).
+static ntt_status plan_batch(ntt_batch_s* b, const ntt_job* jobs, uint32_t n_jobs, std::vector<nttk::VecDesc>& desc) {
+  if (!jobs || n_jobs == 0) return fail(NTT_ERR_ARG, "jobs must be a non-empty array");
+  std::vector<ntt_job> js(jobs, jobs + n_jobs);
   std::vector<ntt_plan_t> plans;
   for (uint32_t j = 0; j < n_jobs; ++j) {
-    const ntt_job& job = b->jobs[j];
+    const ntt_job& job = js[j];
     if (!job.plan || !job.d_data) return fail(NTT_ERR_ARG, "job " + std::to_string(j) + ": NULL plan or data");
     if (reinterpret_cast<uintptr_t>(job.d_data) & 15) return fail(NTT_ERR_ARG, "job data must be 16-byte aligned");
     if (job.n_polys == 0 || job.n_limbs > job.plan->L || job.reserved)
       return fail(NTT_ERR_ARG, "job " + std::to_string(j) + ": bad n_polys, n_limbs or reserved field");
-    if (job.op < NTT_OP_FORWARD || job.op > NTT_OP_FORWARD_INVERSE)
+    if (job.op == 0 || job.op > (NTT_OP_FORWARD | NTT_OP_INVERSE | NTT_OP_MULKEY))
       return fail(NTT_ERR_ARG, "job " + std::to_string(j) + ": bad op");
-    if (job.plan->device != b->jobs[0].plan->device) return fail(NTT_ERR_ARG, "jobs span several devices");
+    if ((job.op & NTT_OP_MULKEY) && (!job.d_key || (reinterpret_cast<uintptr_t>(job.d_key) & 15)))
+      return fail(NTT_ERR_ARG, "job " + std::to_string(j) + ": MULKEY needs a 16-byte aligned key");
+    if (job.plan->device != b->device) return fail(NTT_ERR_ARG, "jobs span several devices");
     if (std::find(plans.begin(), plans.end(), job.plan) == plans.end()) plans.push_back(job.plan);
   }
-  b->device = b->jobs[0].plan->device;
-  hipError_t e;
+  std::vector<ntt_batch_s::Group> groups;
+  desc.clear();
   for (ntt_plan_t plan : plans) {
     ntt_batch_s::Group g;
     g.plan = plan;
-    std::vector<nttk::VecDesc> fwd, inv;
+    std::vector<nttk::VecDesc> fwd, key, inv;
     // limb-major: the polynomials of one limb are adjacent, so launches meet its twiddles together
     for (uint32_t l = 0; l < plan->L; ++l) {
-      for (const ntt_job& job : b->jobs) {
+      for (const ntt_job& job : js) {
         if (job.plan != plan) continue;
         const uint32_t lim = job.n_limbs ? job.n_limbs : plan->L;
         if (l >= lim) continue;
         for (uint32_t p = 0; p < job.n_polys; ++p) {
-          const nttk::VecDesc d{job.d_data + ((uint64_t)p * lim + l) * plan->N, l, 0};
+          nttk::VecDesc d{job.d_data + ((uint64_t)p * lim + l) * plan->N, nullptr, l, 0};
           if (job.op & NTT_OP_FORWARD) fwd.push_back(d);
           if (job.op & NTT_OP_INVERSE) inv.push_back(d);
+          if (job.op & NTT_OP_MULKEY) {
+            d.key = job.d_key + (uint64_t)l * plan->N;
+            key.push_back(d);
+          }
         }
       }
     }
-    for (auto* list : {&fwd, &inv}) {
-      if (list->size() * ((uint64_t)plan->N / 16 + 1) >= (1ull << 31))
-        return fail(NTT_ERR_ARG, "batch too large for one launch");
-    }
-    if ((e = upload(&g.d_fwd, fwd)) != hipSuccess || (e = upload(&g.d_inv, inv)) != hipSuccess) {
-      b->groups.push_back(g);
-      return e == hipErrorOutOfMemory ? fail(NTT_ERR_NOMEM, "descriptor allocation failed")
-                                      : hip_fail(e, "uploading batch descriptors");
-    }
+    for (auto* list : {&fwd, &key, &inv})
+      if (list->size() * ((uint64_t)plan->N / 16 + 1) >= (1ull << 31)) return fail(NTT_ERR_ARG, "batch too large for one launch");
+    g.off_fwd = desc.size();
     g.n_fwd = fwd.size();
+    desc.insert(desc.end(), fwd.begin(), fwd.end());
+    g.off_key = desc.size();
+    g.n_key = key.size();
+    desc.insert(desc.end(), key.begin(), key.end());
+    g.off_inv = desc.size();
     g.n_inv = inv.size();
-    b->groups.push_back(g);
+    desc.insert(desc.end(), inv.begin(), inv.end());
+    groups.push_back(g);
   }
+  b->jobs.swap(js);
+  b->groups.swap(groups);
+  return NTT_OK;
+}
+
+// Copy descriptors into the arena on `st`, behind the batch's last run; the arena grows
+// (after that run has finished) when the new set does not fit.
+static ntt_status upload_batch(ntt_batch_s* b, const std::vector<nttk::VecDesc>& desc, hipStream_t st) {
+  hipError_t e;
+  if (desc.size() > b->cap) {
+    if (b->used_pending && (e = hipEventSynchronize(b->used)) != hipSuccess) return hip_fail(e, "waiting for batch");
+    if (b->upload_pending && (e = hipEventSynchronize(b->uploaded)) != hipSuccess)
+      return hip_fail(e, "waiting for batch upload");
+    if (b->d_desc) (void)hipFree(b->d_desc);
+    if (b->h_desc) (void)hipHostFree(b->h_desc);
+    b->d_desc = b->h_desc = nullptr;
+    b->cap = 0;
+    const uint64_t cap = std::max<uint64_t>(desc.size(), 256);
+    if ((e = hipMalloc(reinterpret_cast<void**>(&b->d_desc), cap * sizeof(nttk::VecDesc))) != hipSuccess ||
+        (e = hipHostMalloc(reinterpret_cast<void**>(&b->h_desc), cap * sizeof(nttk::VecDesc), 0)) != hipSuccess)
+      return e == hipErrorOutOfMemory ? fail(NTT_ERR_NOMEM, "descriptor allocation failed")
+                                      : hip_fail(e, "descriptor allocation");
+    b->cap = cap;
+  }
+  b->drop_graph();
+  if (desc.empty()) return NTT_OK;
+  // the staging buffer may still feed the previous copy; the arena may still feed the last run
+  if (b->upload_pending && (e = hipEventSynchronize(b->uploaded)) != hipSuccess)
+    return hip_fail(e, "waiting for batch upload");
+  if (b->used_pending && (e = hipStreamWaitEvent(st, b->used, 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+  std::copy(desc.begin(), desc.end(), b->h_desc);
+  if ((e = hipMemcpyAsync(b->d_desc, b->h_desc, desc.size() * sizeof(nttk::VecDesc), hipMemcpyHostToDevice, st)) !=
+          hipSuccess ||
+      (e = hipEventRecord(b->uploaded, st)) != hipSuccess)
+    return hip_fail(e, "uploading batch descriptors");
+  b->upload_pending = true;
   return NTT_OK;
 }
 
@@ -609,19 +678,45 @@ ntt_status ntt_batch_create(ntt_batch_t* out, const ntt_job* jobs, uint32_t n_jo
     if (!jobs[0].plan) return fail(NTT_ERR_ARG, "job 0: NULL plan");
     DeviceGuard g(jobs[0].plan->device);
     if (!g.ok) return fail(NTT_ERR_HIP, "cannot select the plans' device");
-    ntt_batch_s* b = new (std::nothrow) ntt_batch_s();
+    std::unique_ptr<ntt_batch_s> b(new (std::nothrow) ntt_batch_s());
     if (!b) return fail(NTT_ERR_NOMEM, "host allocation failed");
-    const ntt_status s = build_batch(b, jobs, n_jobs);
-    if (s != NTT_OK) {
-      delete b;
-      return s;
-    }
-    *out = b;
+    b->device = jobs[0].plan->device;
+    std::vector<nttk::VecDesc> desc;
+    ntt_status s = plan_batch(b.get(), jobs, n_jobs, desc);
+    if (s != NTT_OK) return s;
+    hipError_t e;
+    if ((e = hipEventCreateWithFlags(&b->used, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming)) != hipSuccess)
+      return hip_fail(e, "hipEventCreate");
+    if ((s = upload_batch(b.get(), desc, nullptr)) != NTT_OK) return s;
+    if ((e = hipStreamSynchronize(nullptr)) != hipSuccess) return hip_fail(e, "uploading batch descriptors");
+    *out = b.release();
     return NTT_OK;
   } catch (const std::bad_alloc&) {
     return fail(NTT_ERR_NOMEM, "host allocation failed");
   } catch (...) {
     return fail(NTT_ERR_ARG, "unexpected failure in ntt_batch_create");
+  }
+}
+
+ntt_status ntt_batch_assign(ntt_batch_t b, const ntt_job* jobs, uint32_t n_jobs, void* stream) {
+  try {
+    if (!b) return fail(NTT_ERR_ARG, "batch is NULL");
+    DeviceGuard g(b->device);
+    if (!g.ok) return fail(NTT_ERR_HIP, "cannot select the batch's device");
+    std::vector<nttk::VecDesc> desc;
+    ntt_status s = plan_batch(b, jobs, n_jobs, desc);
+    if (s == NTT_OK) s = upload_batch(b, desc, static_cast<hipStream_t>(stream));
+    if (s != NTT_OK) {   // leave no job whose descriptors may be missing
+      b->jobs.clear();
+      b->groups.clear();
+      b->drop_graph();
+    }
+    return s;
+  } catch (const std::bad_alloc&) {
+    return fail(NTT_ERR_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(NTT_ERR_ARG, "unexpected failure in ntt_batch_assign");
   }
 }
 
@@ -632,11 +727,22 @@ ntt_status ntt_batch_run(ntt_batch_t b, int32_t mode, void* stream) {
     if (!g.ok) return fail(NTT_ERR_HIP, "cannot select the batch's device");
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e = hipSuccess;
+    if (mode < NTT_BATCH_PLAIN || mode > NTT_BATCH_GRAPH) return fail(NTT_ERR_ARG, "unknown batch mode");
+    if (b->jobs.empty()) return NTT_OK;   // emptied by a failed assign
     if (mode == NTT_BATCH_PLAIN) {
       for (const ntt_job& job : b->jobs) {
-        if ((job.op & NTT_OP_FORWARD) && (e = transform(job.plan, job.d_data, job.n_polys, false, st, job.n_limbs)))
+        const ntt_plan_t pl = job.plan;
+        const uint32_t lim = job.n_limbs ? job.n_limbs : pl->L;
+        if ((job.op & NTT_OP_FORWARD) && (e = transform(pl, job.d_data, job.n_polys, false, st, job.n_limbs)))
           break;
-        if ((job.op & NTT_OP_INVERSE) && (e = transform(job.plan, job.d_data, job.n_polys, true, st, job.n_limbs)))
+        if (job.op & NTT_OP_MULKEY) {
+          const uint64_t per = (uint64_t)lim * pl->N;
+          for (uint32_t p = 0; p < job.n_polys && e == hipSuccess; ++p)
+            e = nttk::launch_pointwise(job.d_data + p * per, job.d_key, job.d_data + p * per, pl->d_q, pl->d_mu,
+                                       pl->d_bits, per, pl->logN, lim, st);
+          if (e != hipSuccess) break;
+        }
+        if ((job.op & NTT_OP_INVERSE) && (e = transform(pl, job.d_data, job.n_polys, true, st, job.n_limbs)))
           break;
       }
     } else if (mode == NTT_BATCH_GROUPED) {
@@ -658,6 +764,7 @@ ntt_status ntt_batch_run(ntt_batch_t b, int32_t mode, void* stream) {
     } else {
       return fail(NTT_ERR_ARG, "unknown batch mode");
     }
+    if (e == hipSuccess && (e = hipEventRecord(b->used, st)) == hipSuccess) b->used_pending = true;
     return e == hipSuccess ? NTT_OK : hip_fail(e, "ntt_batch_run");
   } catch (...) {
     return fail(NTT_ERR_ARG, "unexpected failure in ntt_batch_run");

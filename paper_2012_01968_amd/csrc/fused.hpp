@@ -30,6 +30,7 @@
 namespace nttk {
 
 constexpr uint32_t kFusedThreads = 256;
+constexpr int kFusedLR = 4;         // 16 values per lane in both sub-transforms
 constexpr uint32_t kCtrDone = 16;   // counters: [0..7] queue heads, [8] exit count, [16 + v] vector done
 
 __device__ __forceinline__ uint32_t xcc_id() {
@@ -38,11 +39,11 @@ __device__ __forceinline__ uint32_t xcc_id() {
 
 template <int LOGM1, int LOGM2>
 struct FusedShape {
-  using SC = Steps<LOGM1, kLR>;              // column sub-transform, 16 values per lane
+  using SC = Steps<LOGM1, kFusedLR>;         // column sub-transform
   static constexpr int M1 = 1 << LOGM1;      // column length N1
   static constexpr int C = 4096 / M1;        // columns per column tile
   static constexpr int TC = M1 / SC::R;      // lanes per column
-  using RC = RowCfg<LOGM2, (int)kFusedThreads>;   // row tile: V rows of M2
+  using RC = RowCfg<LOGM2, (int)kFusedThreads, kFusedLR>;   // row tile: V rows of M2
   static constexpr int M2 = 1 << LOGM2;
   static constexpr int Tc = M2 / C;          // column tiles per vector
   static constexpr int Tr = M1 / RC::V;      // row tiles per vector
@@ -94,7 +95,7 @@ __device__ __forceinline__ void fwd_col_tile(const PassArgs& a, uint32_t v, uint
 #pragma unroll
       for (int u = 0; u < S::R; ++u) x[u] = lds[S::template idx<k>(t, u) * F::C + c];
     }
-    ct_step<FAST, LOGM1, kLR, k, 0>(x, t, 1u, tabfn, ot, md);
+    ct_step<FAST, LOGM1, kFusedLR, k, 0>(x, t, 1u, tabfn, ot, md);
   });
 #pragma unroll
   for (int u = 0; u < S::R; ++u) colp[(size_t)S::template idx<S::K - 1>(t, u) << LOGM2] = x[u];
@@ -134,7 +135,7 @@ __device__ __forceinline__ void fwd_row_tile(const PassArgs& a, uint32_t v, uint
 #pragma unroll
       for (int u = 0; u < S::R; ++u) x[u] = l[lds_pad(S::template idx<k>(t, u))];
     }
-    ct_step<FAST, LOGM2, kLR, k, OTS>(x, t, base, tabfn, ot, md);
+    ct_step<FAST, LOGM2, kFusedLR, k, OTS>(x, t, base, tabfn, ot, md);
   });
 #pragma unroll
   for (int u = 0; u < S::R; ++u) x[u] = A::fwd_final(x[u], md);
@@ -192,7 +193,7 @@ __device__ __forceinline__ void inv_row_tile(const PassArgs& a, uint32_t v, uint
 #pragma unroll
       for (int u = 0; u < S::R; ++u) x[u] = l[lds_pad(S::template idx<k>(t, u))];
     }
-    gs_step<FAST, LOGM2, kLR, k, OTS, false>(x, t, base, tabfn, ot, md, sc, sc);
+    gs_step<FAST, LOGM2, kFusedLR, k, OTS, false>(x, t, base, tabfn, ot, md, sc, sc);
   });
 #pragma unroll
   for (int u = 0; u < S::R; ++u) rowp[S::template idx<0>(t, u)] = x[u];
@@ -225,7 +226,7 @@ __device__ __forceinline__ void inv_col_tile(const PassArgs& a, uint32_t v, uint
 #pragma unroll
       for (int u = 0; u < S::R; ++u) x[u] = lds[S::template idx<k>(t, u) * F::C + c];
     }
-    gs_step<FAST, LOGM1, kLR, k, 0, true>(x, t, 1u, tabfn, ot, md, sc0, sc1);
+    gs_step<FAST, LOGM1, kFusedLR, k, 0, true>(x, t, 1u, tabfn, ot, md, sc0, sc1);
   });
 #pragma unroll
   for (int u = 0; u < S::R; ++u) colp[(size_t)S::template idx<0>(t, u) << LOGM2] = A::inv_final(x[u], md);

@@ -36,6 +36,28 @@ __global__ __launch_bounds__(256) void pointwise_kernel(const uint64_t* __restri
   }
 }
 
+// Key product over a vector list: vector i (N residues at vecs[i].ptr, prime vecs[i].limb)
+// is replaced by its element-wise product with vecs[i].key.
+__global__ __launch_bounds__(256) void pointwise_list_kernel(const VecDesc* __restrict__ vecs, uint64_t n_pairs,
+                                                             uint32_t logN, const uint64_t* __restrict__ qs,
+                                                             const uint64_t* __restrict__ mus,
+                                                             const uint32_t* __restrict__ bits) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pairs;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t e = i << 1;
+    const VecDesc d = vecs[e >> logN];
+    const uint64_t off = e & ((1ull << logN) - 1);
+    const uint64_t q = qs[d.limb], mu = mus[d.limb];
+    const uint32_t s = bits[d.limb];
+    const ulonglong2 va = *reinterpret_cast<const ulonglong2*>(d.ptr + off);
+    const ulonglong2 vk = *reinterpret_cast<const ulonglong2*>(d.key + off);
+    ulonglong2 vc;
+    vc.x = mulmod_barrett(va.x, vk.x, q, mu, s);
+    vc.y = mulmod_barrett(va.y, vk.y, q, mu, s);
+    *reinterpret_cast<ulonglong2*>(d.ptr + off) = vc;
+  }
+}
+
 bool shape_supported(uint32_t logN, uint32_t logN1, int ots) {
   if (logN < 1 || logN > 17) return false;
   if (logN1 == 0) {
@@ -97,6 +119,16 @@ hipError_t launch_fused(const PassArgs& a, int ots, bool inverse, uint32_t* ctr,
   f.P = n_polys;
   f.lag = lag;
   return inverse ? fused_dispatch<true>(f, ots, max_grid, st) : fused_dispatch<false>(f, ots, max_grid, st);
+}
+
+hipError_t launch_pointwise_list(const VecDesc* vecs, uint64_t n_vec, uint32_t logN, const uint64_t* qs,
+                                 const uint64_t* mus, const uint32_t* bits, hipStream_t st) {
+  const uint64_t pairs = (n_vec << logN) / 2;   // N >= 2: whole pairs per vector
+  if (pairs == 0) return hipSuccess;
+  uint64_t blocks = (pairs + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(pointwise_list_kernel, dim3((uint32_t)blocks), dim3(256), 0, st, vecs, pairs, logN, qs, mus, bits);
+  return hipGetLastError();
 }
 
 hipError_t launch_pointwise(const uint64_t* A, const uint64_t* B, uint64_t* Cc, const uint64_t* qs,

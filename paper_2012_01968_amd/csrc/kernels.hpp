@@ -7,6 +7,7 @@ namespace nttk {
 
 struct Tw;
 struct PassArgs;
+struct VecDesc;
 
 // Whether a (log2 N, log2 N1, OT stages) combination has kernels built in.
 bool shape_supported(uint32_t logN, uint32_t logN1, int ot_stages);
@@ -24,6 +25,10 @@ struct FusedArgs;
 bool fused_supported(uint32_t logN, uint32_t logN1, int ot_stages);
 hipError_t launch_fused(const PassArgs& a, int ot_stages, bool inverse, uint32_t* ctr, uint32_t n_polys,
                         uint32_t lag, uint32_t max_grid, hipStream_t st);
+
+// Every vector of a list times its key vector, in place (Barrett products).
+hipError_t launch_pointwise_list(const VecDesc* vecs, uint64_t n_vec, uint32_t logN, const uint64_t* qs,
+                                 const uint64_t* mus, const uint32_t* bits, hipStream_t st);
 
 // C = A * B mod q_l element-wise over n_elems elements of a [n_vec][N] batch.
 hipError_t launch_pointwise(const uint64_t* A, const uint64_t* B, uint64_t* C, const uint64_t* qs,

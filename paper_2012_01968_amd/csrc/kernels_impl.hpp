@@ -7,7 +7,10 @@
 
 namespace nttk {
 
-constexpr int kLR = 4;          // 16 values per lane per register step
+#ifndef NTTK_LR
+#define NTTK_LR 4
+#endif
+constexpr int kLR = NTTK_LR;    // 2^kLR values per lane per register step
 #ifndef NTTK_COL_WIDTH
 #define NTTK_COL_WIDTH 8
 #endif
@@ -35,9 +38,9 @@ __device__ __forceinline__ uint64_t limb_major_vec(uint64_t lp, uint32_t L, uint
 
 __device__ __forceinline__ uint32_t lds_pad(uint32_t r) { return r + (r >> 4); }
 
-template <int LOGM, int NTH = kRowThreads>
+template <int LOGM, int NTH = kRowThreads, int LR = kLR>
 struct RowCfg {
-  using S = Steps<LOGM, kLR>;
+  using S = Steps<LOGM, LR>;
   static constexpr int M = 1 << LOGM;
   static constexpr int T = M / S::R;                    // lanes per row
   static constexpr int V = T >= NTH ? 1 : NTH / T;      // rows per workgroup

@@ -43,10 +43,20 @@ __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) { return __u
 
 __device__ __forceinline__ uint64_t csub(uint64_t x, uint64_t m) { return x >= m ? x - m : x; }
 
-// x - m when x >= m, else x; needs x < 2^63 and m < 2^63 (negm = 2^64 - m).
+__device__ __forceinline__ uint64_t make_u64(uint32_t lo, uint32_t hi) {
+  return __builtin_bit_cast(uint64_t, (uint2{lo, hi}));
+}
+
+// x - m when x >= m, else x; needs x < 2^63 and m < 2^63 (negm = 2^64 - m).  The sign of
+// x - m is spread to a mask and two bit-field selects pick the halves, which keeps the
+// select off the VCC path (no compare, no VALU-to-VCC hazard).
 __device__ __forceinline__ uint64_t csub_sign(uint64_t x, uint64_t negm) {
   const uint64_t d = x + negm;
-  return (int64_t)d < 0 ? x : d;
+  const uint32_t m = (uint32_t)((int32_t)(uint32_t)(d >> 32) >> 31);
+  uint32_t lo, hi;
+  asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(lo) : "v"(m), "v"((uint32_t)x), "v"((uint32_t)d));
+  asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(hi) : "v"(m), "v"((uint32_t)(x >> 32)), "v"((uint32_t)(d >> 32)));
+  return make_u64(lo, hi);
 }
 
 template <bool FAST>
@@ -96,6 +106,12 @@ struct Arith<false> {
   }
   static __device__ __forceinline__ uint64_t fwd_final(uint64_t x, const Mod& m) { return csub(csub(x, m.q2), m.q); }
   static __device__ __forceinline__ uint64_t inv_final(uint64_t x, const Mod& m) { return csub(x, m.q); }
+  template <int NB>
+  static __device__ __forceinline__ void mul_n(uint64_t (&r)[NB], const uint64_t (&b)[NB], const Tw (&t)[NB],
+                                               const Mod& m) {
+#pragma unroll
+    for (int k = 0; k < NB; ++k) r[k] = mul(b[k], t[k], m);
+  }
 };
 
 template <>
@@ -111,7 +127,32 @@ struct Arith<true> {
     const uint32_t c0 = (uint32_t)qh, c1 = (uint32_t)(qh >> 32);
     const uint64_t lo = (uint64_t)b0 * w0 + (uint64_t)c0 * n0;
     const uint32_t hi = (uint32_t)(lo >> 32) + b0 * w1 + b1 * w0 + c0 * n1 + c1 * n0;
-    return ((uint64_t)hi << 32) | (uint32_t)lo;
+    return make_u64((uint32_t)lo, hi);
+  }
+
+  // NB independent products b[k] * t[k] mod q, written phase by phase so that the
+  // multiply chains of different butterflies sit next to each other for the scheduler.
+  template <int NB>
+  static __device__ __forceinline__ void mul_n(uint64_t (&r)[NB], const uint64_t (&b)[NB], const Tw (&t)[NB],
+                                               const Mod& m) {
+    const uint32_t n0 = (uint32_t)m.nq, n1 = (uint32_t)(m.nq >> 32);
+    uint32_t h1[NB], h2[NB];
+    uint64_t qh[NB], lo[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) h1[k] = __umulhi((uint32_t)b[k], (uint32_t)(t[k].wb >> 32));
+#pragma unroll
+    for (int k = 0; k < NB; ++k) h2[k] = __umulhi((uint32_t)(b[k] >> 32), (uint32_t)t[k].wb);
+#pragma unroll
+    for (int k = 0; k < NB; ++k) qh[k] = (uint64_t)(uint32_t)(b[k] >> 32) * (uint32_t)(t[k].wb >> 32) + h1[k] + h2[k];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) lo[k] = (uint64_t)(uint32_t)b[k] * (uint32_t)t[k].w + (uint64_t)(uint32_t)qh[k] * n0;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      const uint32_t b0 = (uint32_t)b[k], b1 = (uint32_t)(b[k] >> 32);
+      const uint32_t hi = (uint32_t)(lo[k] >> 32) + b0 * (uint32_t)(t[k].w >> 32) + b1 * (uint32_t)t[k].w +
+                          (uint32_t)qh[k] * n1 + (uint32_t)(qh[k] >> 32) * n0;
+      r[k] = make_u64((uint32_t)lo[k], hi);
+    }
   }
   // Cooley-Tukey: X, Y in [0, 8q) -> X + WY, X - WY in [0, 8q).
   static __device__ __forceinline__ void ct(uint64_t& X, uint64_t& Y, const Tw& t, const Mod& m) {

@@ -25,6 +25,7 @@ namespace nttk {
 // One limb-vector of a vector-list launch: its residues and the plan limb (prime) it uses.
 struct VecDesc {
   uint64_t* ptr;
+  const uint64_t* key;   // key-product launches: the key vector this vector is multiplied by
   uint32_t limb;
   uint32_t pad;
 };
@@ -122,18 +123,47 @@ __device__ __forceinline__ void ct_step(uint64_t (&x)[NR], uint32_t t, uint32_t 
     constexpr int bit = decltype(bit_c)::value;
     constexpr int s = LOGM - 1 - bit;
     constexpr int i = bit - lo;
+    if constexpr (FAST) {
+      // all R/2 butterflies of the stage at once: twiddles, X reductions, products, outputs
+      constexpr int H = S::R / 2;
+      Tw w[H], w2[H];
+      uint64_t xs[H], ys[H], v[H];
 #pragma unroll
-    for (int u = 0; u < S::R; ++u) {
-      if (u & (1 << i)) continue;
-      const uint32_t r = S::template idx<K_STEP>(t, (uint32_t)u);
-      const uint32_t ix = (base << s) + (r >> (bit + 1));
-      if constexpr (OTS > 0 && s >= LOGM - OTS) {
-        Tw a, c;
-        ot.get(ix, a, c);
-        A::ct2(x[u], x[u | (1 << i)], a, c, md);
-      } else {
-        const Tw w = tab(ix);
-        A::ct(x[u], x[u | (1 << i)], w, md);
+      for (int k = 0; k < H; ++k) {
+        const int u = ((k >> i) << (i + 1)) | (k & ((1 << i) - 1));   // k-th index with bit i clear
+        const uint32_t r = S::template idx<K_STEP>(t, (uint32_t)u);
+        const uint32_t ix = (base << s) + (r >> (bit + 1));
+        if constexpr (OTS > 0 && s >= LOGM - OTS) ot.get(ix, w[k], w2[k]);
+        else w[k] = tab(ix);
+        ys[k] = x[u | (1 << i)];
+      }
+#pragma unroll
+      for (int k = 0; k < H; ++k) {
+        const int u = ((k >> i) << (i + 1)) | (k & ((1 << i) - 1));
+        xs[k] = csub_sign(x[u], md.nq4);
+      }
+      A::template mul_n<H>(v, ys, w, md);
+      if constexpr (OTS > 0 && s >= LOGM - OTS) A::template mul_n<H>(v, v, w2, md);
+#pragma unroll
+      for (int k = 0; k < H; ++k) {
+        const int u = ((k >> i) << (i + 1)) | (k & ((1 << i) - 1));
+        x[u] = xs[k] + v[k];
+        x[u | (1 << i)] = xs[k] + md.q4 - v[k];
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < S::R; ++u) {
+        if (u & (1 << i)) continue;
+        const uint32_t r = S::template idx<K_STEP>(t, (uint32_t)u);
+        const uint32_t ix = (base << s) + (r >> (bit + 1));
+        if constexpr (OTS > 0 && s >= LOGM - OTS) {
+          Tw a, c;
+          ot.get(ix, a, c);
+          A::ct2(x[u], x[u | (1 << i)], a, c, md);
+        } else {
+          const Tw w = tab(ix);
+          A::ct(x[u], x[u | (1 << i)], w, md);
+        }
       }
     }
   });
@@ -155,6 +185,33 @@ __device__ __forceinline__ void gs_step(uint64_t (&x)[NR], uint32_t t, uint32_t 
     constexpr int bit = decltype(bit_c)::value;
     constexpr int s = LOGM - 1 - bit;
     constexpr int i = bit - lo;
+    if constexpr (FAST && !(SCALE0 && s == 0)) {
+      constexpr int H = S::R / 2;
+      Tw w[H], w2[H];
+      uint64_t ds[H], v[H];
+#pragma unroll
+      for (int k = 0; k < H; ++k) {
+        const int u = ((k >> i) << (i + 1)) | (k & ((1 << i) - 1));
+        const uint32_t r = S::template idx<K_STEP>(t, (uint32_t)u);
+        const uint32_t ix = (base << s) + (r >> (bit + 1));
+        if constexpr (OTS > 0 && s >= LOGM - OTS) ot.get(ix, w[k], w2[k]);
+        else w[k] = tab(ix);
+      }
+#pragma unroll
+      for (int k = 0; k < H; ++k) {
+        const int u = ((k >> i) << (i + 1)) | (k & ((1 << i) - 1));
+        const uint64_t X = x[u], Y = x[u | (1 << i)];
+        ds[k] = X + md.q4 - Y;
+        x[u] = csub_sign(X + Y, md.nq4);
+      }
+      A::template mul_n<H>(v, ds, w, md);
+      if constexpr (OTS > 0 && s >= LOGM - OTS) A::template mul_n<H>(v, v, w2, md);
+#pragma unroll
+      for (int k = 0; k < H; ++k) {
+        const int u = ((k >> i) << (i + 1)) | (k & ((1 << i) - 1));
+        x[u | (1 << i)] = v[k];
+      }
+    } else {
 #pragma unroll
     for (int u = 0; u < S::R; ++u) {
       if (u & (1 << i)) continue;
@@ -172,6 +229,7 @@ __device__ __forceinline__ void gs_step(uint64_t (&x)[NR], uint32_t t, uint32_t 
           A::gs(x[u], x[u | (1 << i)], w, md);
         }
       }
+    }
     }
   });
 }

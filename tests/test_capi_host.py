@@ -89,3 +89,17 @@ def test_argument_errors_are_synchronous(lib):
     lib.ntt_forward.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p]
     lib.ntt_forward.restype = ctypes.c_int
     assert lib.ntt_forward(None, None, 1, None) == -1
+
+
+def test_batch_argument_errors(lib):
+    vp = ctypes.c_void_p
+    lib.ntt_batch_create.argtypes = [ctypes.POINTER(vp), vp, ctypes.c_uint32]
+    lib.ntt_batch_assign.argtypes = [vp, vp, ctypes.c_uint32, vp]
+    lib.ntt_batch_run.argtypes = [vp, ctypes.c_int32, vp]
+    lib.ntt_batch_destroy.argtypes = [vp]
+    h = vp(99)
+    assert lib.ntt_batch_create(None, None, 0) == -1
+    assert lib.ntt_batch_create(ctypes.byref(h), None, 0) == -1 and h.value is None
+    assert lib.ntt_batch_assign(None, None, 0, None) == -1
+    assert lib.ntt_batch_run(None, 0, None) == -1
+    assert lib.ntt_batch_destroy(None) == 0

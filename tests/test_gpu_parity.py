@@ -347,3 +347,87 @@ def test_batch_uneven_jobs(mode):
     finally:
         for p in plans.values():
             p.destroy()
+
+
+@pytest.mark.parametrize("mode", ["plain", "grouped", "graph"])
+def test_batch_mulkey_jobs(mode):
+    """Forward, product with a resident NTT-domain key, inverse, as one job: the result is
+    the negacyclic product with the key polynomial, per limb (schoolbook-checked on a small
+    case, oracle NTT product on the rest)."""
+    n_max = 1 << 15
+    chain = synth.gen_primes(1200, n_max, 60, 8)
+    plans = {logN: ntt.ntt_plan_create(1 << logN, chain) for logN in (5, 12, 15)}
+    spec = [(5, 3, 2), (12, 8, 1), (15, 5, 2), (12, 2, 3), (15, 8, 1)]
+    try:
+        jobs, bufs, want = [], [], []
+        keys = {}
+        for logN in plans:
+            N = 1 << logN
+            coeff = synth.residue_batch(1300 + logN, chain, N, 1)
+            keys[logN] = (coeff, oracle.forward(coeff, chain, oracle.roots(chain, N), THREADS),)
+        for k, (logN, limbs, polys) in enumerate(spec):
+            N = 1 << logN
+            primes = chain[:limbs]
+            psis = oracle.roots(primes, N)
+            data = synth.residue_batch(1400 + k, primes, N, polys)
+            coeff, key_ntt = keys[logN]
+            key_coeff = coeff.reshape(len(chain), N)[:limbs]
+            w = oracle.polymul(data.reshape(polys * limbs, N), np.tile(key_coeff, (polys, 1)), primes, psis,
+                               THREADS).reshape(data.shape)
+            if logN == 5:   # pin the small case to the schoolbook product as well
+                a = data.reshape(polys, limbs, N)
+                for p in range(polys):
+                    for l in range(limbs):
+                        sb = oracle.schoolbook(a[p, l], key_coeff[l], primes[l])
+                        assert np.array_equal(w.reshape(polys, limbs, N)[p, l], sb)
+            d = dev(data)
+            dk = dev(key_ntt.reshape(len(chain), N)[:limbs])
+            bufs.append((d, dk))
+            want.append(w)
+            jobs.append((plans[logN], d, polys, limbs if limbs < len(chain) else 0,
+                         ntt.OP_FORWARD | ntt.OP_MULKEY | ntt.OP_INVERSE, dk))
+        batch = ntt.ntt_batch_create(jobs)
+        m = {"plain": ntt.BATCH_PLAIN, "grouped": ntt.BATCH_GROUPED, "graph": ntt.BATCH_GRAPH}[mode]
+        ntt.ntt_batch_run(batch, m)
+        torch.cuda.synchronize()
+        for (d, _), w in zip(bufs, want):
+            assert np.array_equal(host(d), w)
+        batch.destroy()
+    finally:
+        for p in plans.values():
+            p.destroy()
+
+
+def test_batch_assign_reuse():
+    """One batch object, reassigned on a stream to job sets of growing and shrinking size;
+    each run matches the oracle, and a graph captured before a reassign is not reused."""
+    chain = synth.gen_primes(1500, 1 << 13, 60, 4)
+    plans = {logN: ntt.ntt_plan_create(1 << logN, chain) for logN in (11, 13)}
+    st = torch.cuda.Stream()
+    rounds = [[(11, 2, 1)], [(13, 4, 3), (11, 4, 2), (11, 1, 5)], [(13, 1, 1)], [(11, 3, 40), (13, 4, 9)]]
+    batch = None
+    try:
+        for r, spec in enumerate(rounds):
+            jobs, bufs, want = [], [], []
+            for k, (logN, limbs, polys) in enumerate(spec):
+                N = 1 << logN
+                primes = chain[:limbs]
+                data = synth.residue_batch(1600 + 10 * r + k, primes, N, polys)
+                want.append(oracle.forward(data, primes, oracle.roots(primes, N), THREADS))
+                d = dev(data)
+                bufs.append(d)
+                jobs.append((plans[logN], d, polys, limbs if limbs < len(chain) else 0, ntt.OP_FORWARD))
+            torch.cuda.synchronize()
+            if batch is None:
+                batch = ntt.ntt_batch_create(jobs)
+            else:
+                ntt.ntt_batch_assign(batch, jobs, st)
+            ntt.ntt_batch_run(batch, ntt.BATCH_GRAPH if r % 2 else ntt.BATCH_GROUPED, st)
+            st.synchronize()
+            for d, w in zip(bufs, want):
+                assert np.array_equal(host(d), w), f"round {r}"
+    finally:
+        if batch is not None:
+            batch.destroy()
+        for p in plans.values():
+            p.destroy()
