@@ -105,6 +105,10 @@ def main() -> int:
     ap.add_argument("--log2-n1", type=int, default=0)
     ap.add_argument("--rotate-gib", type=float, default=1.25, help="total size of the rotating input copies")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
+                    help="length of the Poisson request stream of the serving section (0 skips it)")
+    ap.add_argument("--serve-rate", type=float, default=2000.0, help="request arrival rate (1/s)")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch section")
     ap.add_argument("--profile-run", action="store_true",
                     help="counter-collection driver: --steps steps of one twiddle mode (no timing, no JSON), "
                          "then one plain device copy of a ciphertext for the counters' byte calibration")
@@ -244,6 +248,12 @@ def main() -> int:
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(host, primes, N, r["plan"], bufs, dev0, n_limb_ntts)
+    for m in results:
+        results[m]["plan"].destroy()
+    del bufs
+    torch.cuda.empty_cache()
+    uneven = None if args.no_uneven else uneven_batch_bench(args)
+    serving = serve_bench(args) if args.serve_seconds > 0 else None
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "limb-NTTs/s", "n_gpus": 1,
@@ -263,12 +273,136 @@ def main() -> int:
         "kernel_us": {k: round(v * 1e3, 2) for k, v in r["kms"].items()},
         "modes_us_per_step": {m: round(results[m]["ms"] * 1e3, 2) for m in results},
         "roundtrip_ok": r["roundtrip_ok"],
+        "uneven_batch": uneven,
+        "serving": serving,
         "source_hash": src_hash,
     }
-    for m in results:
-        results[m]["plan"].destroy()
     print(json.dumps(out), flush=True)
     return 0
+
+
+UNEVEN = dict(polys=256, logNs=(13, 14, 15, 16, 17), weights=(0.1, 0.2, 0.3, 0.3, 0.1), L=(4, 60), bits=60,
+              seed=4)
+
+
+def uneven_batch_bench(args):
+    """256 independent polynomials of uneven N and limb count, forward then inverse NTT
+    each, as one batch: one plain call sequence per polynomial, grouped launches, and the
+    grouped launches replayed from a captured hipGraph."""
+    import torch
+    import synth
+    import paper_2012_01968_amd as ntt
+
+    cfg = UNEVEN
+    Lmax = cfg["L"][1]
+    chain = synth.gen_primes(cfg["seed"], 1 << max(cfg["logNs"]), cfg["bits"], Lmax)
+    rng = np.random.default_rng(cfg["seed"])
+    logNs = rng.choice(cfg["logNs"], size=cfg["polys"], p=cfg["weights"])
+    Ls = rng.integers(cfg["L"][0], cfg["L"][1] + 1, size=cfg["polys"])
+    plans = {int(k): ntt.ntt_plan_create(1 << int(k), chain) for k in cfg["logNs"]}
+    src = {k: torch.from_numpy(synth.residue_batch(cfg["seed"] + k, chain, 1 << k, 1).view(np.int64)).to("cuda")
+           .view(Lmax, 1 << k) for k in plans}
+    jobs, bufs = [], []
+    for i, (k, L) in enumerate(zip(logNs.tolist(), Ls.tolist())):
+        b = src[k][:L].clone()
+        bufs.append(b)
+        jobs.append((plans[k], b, 1, L if L < Lmax else 0, ntt.OP_FORWARD_INVERSE))
+    limb_ntts = 2 * int(Ls.sum())
+    data_gib = sum(b.numel() for b in bufs) * 8 / 2**30
+    batch = ntt.ntt_batch_create(jobs)
+    out = {"workload": f"{cfg['polys']} polys, N from 2^13..2^17 (weights {list(cfg['weights'])}), "
+                       f"L uniform in [{cfg['L'][0]}, {cfg['L'][1]}], forward+inverse each (seed {cfg['seed']})",
+           "limb_ntts_per_step": limb_ntts, "data_gib": round(data_gib, 3),
+           "polys_by_logN": {int(k): int((logNs == k).sum()) for k in cfg["logNs"]}}
+    steps = max(5, min(args.steps, 40))
+    for name, mode in (("plain", ntt.BATCH_PLAIN), ("grouped", ntt.BATCH_GROUPED), ("graph", ntt.BATCH_GRAPH)):
+        for _ in range(3):
+            ntt.ntt_batch_run(batch, mode)
+        torch.cuda.synchronize()
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        evs[0].record()
+        for i in range(steps):
+            ntt.ntt_batch_run(batch, mode)
+            evs[i + 1].record()
+        torch.cuda.synchronize()
+        per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(steps)])
+        ms = evs[0].elapsed_time(evs[-1]) / steps
+        out[name] = {"ms_per_step": round(ms, 4), "limb_ntts_per_s": round(limb_ntts / (ms * 1e-3), 1),
+                     "p50_ms": round(float(np.percentile(per, 50)), 4),
+                     "p99_ms": round(float(np.percentile(per, 99)), 4)}
+        log(f"[uneven {name}] {ms:.3f} ms/step  {limb_ntts / ms / 1e3:.3f} M limb-NTTs/s")
+    ok = all(torch.equal(b, src[k][:L]) for b, k, L in zip(bufs, logNs.tolist(), Ls.tolist()))
+    out["roundtrip_ok"] = bool(ok)
+    out["graph_vs_plain"] = round(out["plain"]["ms_per_step"] / out["graph"]["ms_per_step"], 3)
+    batch.destroy()
+    for p in plans.values():
+        p.destroy()
+    return out
+
+
+SERVE = dict(logNs=(14, 15, 16), L=(8, 45), polys=2, bits=60, seed=5, lanes=3, capacity_gib=8.0)
+
+
+def serve_bench(args):
+    """Poisson request stream: each request is one ciphertext (2 polys) that needs the
+    forward NTT, a product with a resident NTT-domain key and the inverse NTT.  The
+    continuous-batching loop and the one-launch-per-request path serve the same stream;
+    a saturated run (every request waiting at t=0) gives each one's peak rate."""
+    import torch
+    import synth
+    import paper_2012_01968_amd as ntt
+    from paper_2012_01968_amd.serve import GpuExecutor, Request, Server
+
+    cfg = SERVE
+    Lmax = cfg["L"][1]
+    chain = synth.gen_primes(cfg["seed"], 1 << max(cfg["logNs"]), cfg["bits"], Lmax)
+    plans, keys, src = {}, {}, {}
+    for k in cfg["logNs"]:
+        N = 1 << k
+        plans[N] = ntt.ntt_plan_create(N, chain)
+        key = torch.from_numpy(synth.residue_batch(cfg["seed"] * 100 + k, chain, N, 1).view(np.int64)).to("cuda")
+        ntt.ntt_forward(plans[N], key)
+        keys[N] = key.view(Lmax, N)
+        src[N] = torch.from_numpy(synth.residue_batch(cfg["seed"] + k, chain, N, cfg["polys"]).view(np.int64)) \
+            .to("cuda").view(cfg["polys"], Lmax, N)
+    torch.cuda.synchronize()
+
+    def requests(n, rate, seed):
+        rng = np.random.default_rng(seed)
+        t = np.cumsum(rng.exponential(1.0 / rate, n)) if rate > 0 else np.zeros(n)
+        ks = rng.choice(cfg["logNs"], size=n)
+        Ls = rng.integers(cfg["L"][0], cfg["L"][1] + 1, size=n)
+        return [Request(i, 1 << int(k), int(L), float(t[i]), polys=cfg["polys"], payload=src[1 << int(k)][:, :int(L)])
+                for i, (k, L) in enumerate(zip(ks.tolist(), Ls.tolist()))]
+
+    cap = int(cfg["capacity_gib"] * 2**30)
+    n = int(round(args.serve_rate * args.serve_seconds))
+    out = {"workload": f"Poisson arrivals at {args.serve_rate:g}/s for {args.serve_seconds:g} s ({n} requests, "
+                       f"seed {cfg['seed']}); request = 2 polys, N in {{2^14, 2^15, 2^16}}, L uniform in "
+                       f"[{cfg['L'][0]}, {cfg['L'][1]}]; forward NTT, product with resident key, inverse NTT",
+           "arena_gib": cfg["capacity_gib"], "lanes": cfg["lanes"]}
+    for policy, mode, lanes in (("continuous", ntt.BATCH_GROUPED, cfg["lanes"]), ("per_request", ntt.BATCH_PLAIN, 1)):
+        ex = GpuExecutor(plans, keys, cap, lanes=lanes, mode=mode)
+        Server(ex, cap, policy=policy).run(requests(64, 0, 99))             # warm-up
+        st = Server(ex, cap, policy=policy).run(requests(n, args.serve_rate, cfg["seed"]))
+        sat = Server(ex, cap, policy=policy).run(requests(2000, 0, cfg["seed"] + 1))
+        ex.close()
+        out[policy] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.as_dict().items()}
+        out[policy + "_saturated"] = {"requests": 2000, "throughput_rps": round(sat.throughput_rps, 1),
+                                      "p50_ms": round(sat.p50_ms, 3), "p99_ms": round(sat.p99_ms, 3),
+                                      "mean_batch": round(sat.mean_batch, 2), "peak_gib": round(sat.peak_bytes / 2**30, 3)}
+        log(f"[serve {policy}] {st.completed} done, p50 {st.p50_ms:.3f} ms p99 {st.p99_ms:.3f} ms, "
+            f"{st.throughput_rps:.0f} req/s, mean batch {st.mean_batch:.2f}; saturated {sat.throughput_rps:.0f} req/s "
+            f"(p99 {sat.p99_ms:.1f} ms, mean batch {sat.mean_batch:.1f})")
+        del ex
+        torch.cuda.empty_cache()
+    for p in plans.values():
+        p.destroy()
+    c, pr = out["continuous"], out["per_request"]
+    out["p99_ratio_plain_over_continuous"] = round(pr["p99_ms"] / c["p99_ms"], 3)
+    out["saturated_speedup"] = round(out["continuous_saturated"]["throughput_rps"]
+                                     / out["per_request_saturated"]["throughput_rps"], 3)
+    return out
 
 
 def cpu_baseline(host, primes, N, plan, bufs, dev0, n_limb_ntts):
