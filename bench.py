@@ -108,6 +108,8 @@ def main() -> int:
     ap.add_argument("--serve-seconds", type=float, default=30.0,
                     help="length of the Poisson request stream of the serving section (0 skips it)")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="request arrival rate (1/s)")
+    ap.add_argument("--serve-high-rate", type=float, default=12000.0,
+                    help="arrival rate of a second, 5-second stream above the per-request path's capacity (0 skips)")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch section")
     ap.add_argument("--profile-run", action="store_true",
                     help="counter-collection driver: --steps steps of one twiddle mode (no timing, no JSON), "
@@ -385,9 +387,20 @@ def serve_bench(args):
         ex = GpuExecutor(plans, keys, cap, lanes=lanes, mode=mode)
         Server(ex, cap, policy=policy).run(requests(64, 0, 99))             # warm-up
         st = Server(ex, cap, policy=policy).run(requests(n, args.serve_rate, cfg["seed"]))
+        hi = None
+        if args.serve_high_rate > 0:
+            hi = Server(ex, cap, policy=policy).run(requests(int(5 * args.serve_high_rate), args.serve_high_rate,
+                                                            cfg["seed"] + 2))
         sat = Server(ex, cap, policy=policy).run(requests(2000, 0, cfg["seed"] + 1))
         ex.close()
         out[policy] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.as_dict().items()}
+        if hi is not None:
+            out[policy + "_high_load"] = {"rate": args.serve_high_rate, "requests": hi.completed,
+                                          "throughput_rps": round(hi.throughput_rps, 1), "p50_ms": round(hi.p50_ms, 3),
+                                          "p99_ms": round(hi.p99_ms, 3), "mean_batch": round(hi.mean_batch, 2),
+                                          "peak_gib": round(hi.peak_bytes / 2**30, 3)}
+            log(f"[serve {policy} @ {args.serve_high_rate:g}/s] p50 {hi.p50_ms:.3f} ms p99 {hi.p99_ms:.3f} ms, "
+                f"{hi.throughput_rps:.0f} req/s, mean batch {hi.mean_batch:.2f}")
         out[policy + "_saturated"] = {"requests": 2000, "throughput_rps": round(sat.throughput_rps, 1),
                                       "p50_ms": round(sat.p50_ms, 3), "p99_ms": round(sat.p99_ms, 3),
                                       "mean_batch": round(sat.mean_batch, 2), "peak_gib": round(sat.peak_bytes / 2**30, 3)}
@@ -400,6 +413,9 @@ def serve_bench(args):
         p.destroy()
     c, pr = out["continuous"], out["per_request"]
     out["p99_ratio_plain_over_continuous"] = round(pr["p99_ms"] / c["p99_ms"], 3)
+    if "continuous_high_load" in out:
+        out["high_load_p99_ratio_plain_over_continuous"] = round(
+            out["per_request_high_load"]["p99_ms"] / out["continuous_high_load"]["p99_ms"], 3)
     out["saturated_speedup"] = round(out["continuous_saturated"]["throughput_rps"]
                                      / out["per_request_saturated"]["throughput_rps"], 3)
     return out

@@ -83,12 +83,17 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void fwd_row_kernel(PassArgs a) {
     ot.b = a.ot_log2_base;
   }
   auto tabfn = [&](uint32_t ix) { return tab[ix]; };
-  uint64_t* rowp = vr.base + (g & (N1 - 1)) * C::M;
+  gu64* rowp = vr.base + (g & (N1 - 1)) * C::M;
   uint64_t* l = lds + v * C::PITCH;
 
   uint64_t x[S::R];
+  if (valid) {
 #pragma unroll
-  for (int u = 0; u < S::R; ++u) x[u] = valid ? rowp[S::template idx<0>(t, u)] : 0;
+    for (int u = 0; u < S::R; ++u) x[u] = rowp[S::template idx<0>(t, u)];
+  } else {
+#pragma unroll
+    for (int u = 0; u < S::R; ++u) x[u] = 0;
+  }
 
   static_for<0, S::K>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
@@ -155,12 +160,17 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void inv_row_kernel(PassArgs a) {
     sc1 = a.scale[2 * limb + 1];
   }
   auto tabfn = [&](uint32_t ix) { return tab[ix]; };
-  uint64_t* rowp = vr.base + (g & (N1 - 1)) * C::M;
+  gu64* rowp = vr.base + (g & (N1 - 1)) * C::M;
   uint64_t* l = lds + v * C::PITCH;
 
   uint64_t x[S::R];
+  if (valid) {
 #pragma unroll
-  for (int u = 0; u < S::R; ++u) x[u] = valid ? rowp[S::template idx<0>(t, u)] : 0;
+    for (int u = 0; u < S::R; ++u) x[u] = rowp[S::template idx<0>(t, u)];
+  } else {
+#pragma unroll
+    for (int u = 0; u < S::R; ++u) x[u] = 0;
+  }
   if constexpr (S::K > 1) {
 #pragma unroll
     for (int u = 0; u < S::R; ++u) l[lds_pad(S::template idx<0>(t, u))] = x[u];
@@ -225,7 +235,7 @@ __global__ __launch_bounds__(ColCfg<LOGM>::NT) void fwd_col_kernel(PassArgs a) {
   const Mod md(a.q[limb]);
   const Tw* tab = a.tw + ((size_t)limb << a.logN);
   for (uint32_t i = tid; i < (uint32_t)C::M; i += C::NT) twl[i] = tab[i];
-  uint64_t* colp = vr.base + cg * C::W + c;
+  gu64* colp = vr.base + cg * C::W + c;
 
   uint64_t x[S::R];
 #pragma unroll
@@ -271,7 +281,7 @@ __global__ __launch_bounds__(ColCfg<LOGM>::NT) void inv_col_kernel(PassArgs a) {
   const Tw* tab = a.tw + ((size_t)limb << a.logN);
   for (uint32_t i = tid; i < (uint32_t)C::M; i += C::NT) twl[i] = tab[i];
   const Tw sc0 = a.scale[2 * limb], sc1 = a.scale[2 * limb + 1];
-  uint64_t* colp = vr.base + cg * C::W + c;
+  gu64* colp = vr.base + cg * C::W + c;
 
   uint64_t x[S::R];
 #pragma unroll

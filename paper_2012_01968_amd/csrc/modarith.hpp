@@ -47,6 +47,15 @@ __device__ __forceinline__ uint64_t make_u64(uint32_t lo, uint32_t hi) {
   return __builtin_bit_cast(uint64_t, (uint2{lo, hi}));
 }
 
+// a + b on 32 bits.  Written as one instruction so that the compiler keeps the high word
+// of a 64-bit result as a separate 32-bit add instead of widening it into a 64-bit add
+// (which costs a register move to zero-extend the operand).
+__device__ __forceinline__ uint32_t add_u32(uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("v_add_u32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
 // x - m when x >= m, else x; needs x < 2^63 and m < 2^63 (negm = 2^64 - m).  The sign of
 // x - m is spread to a mask and two bit-field selects pick the halves, which keeps the
 // select off the VCC path (no compare, no VALU-to-VCC hazard).
@@ -123,11 +132,11 @@ struct Arith<true> {
     const uint32_t s0 = (uint32_t)t.wb, s1 = (uint32_t)(t.wb >> 32);
     const uint32_t n0 = (uint32_t)m.nq, n1 = (uint32_t)(m.nq >> 32);
     const uint32_t h1 = __umulhi(b0, s1), h2 = __umulhi(b1, s0);
-    const uint64_t qh = (uint64_t)b1 * s1 + h1 + h2;
+    const uint64_t qh = (uint64_t)b1 * s1 + ((uint64_t)h1 + h2);
     const uint32_t c0 = (uint32_t)qh, c1 = (uint32_t)(qh >> 32);
     const uint64_t lo = (uint64_t)b0 * w0 + (uint64_t)c0 * n0;
-    const uint32_t hi = (uint32_t)(lo >> 32) + b0 * w1 + b1 * w0 + c0 * n1 + c1 * n0;
-    return make_u64((uint32_t)lo, hi);
+    const uint32_t cross = b0 * w1 + b1 * w0 + c0 * n1 + c1 * n0;
+    return make_u64((uint32_t)lo, add_u32((uint32_t)(lo >> 32), cross));
   }
 
   // NB independent products b[k] * t[k] mod q, written phase by phase so that the
@@ -143,15 +152,16 @@ struct Arith<true> {
 #pragma unroll
     for (int k = 0; k < NB; ++k) h2[k] = __umulhi((uint32_t)(b[k] >> 32), (uint32_t)t[k].wb);
 #pragma unroll
-    for (int k = 0; k < NB; ++k) qh[k] = (uint64_t)(uint32_t)(b[k] >> 32) * (uint32_t)(t[k].wb >> 32) + h1[k] + h2[k];
+    for (int k = 0; k < NB; ++k)
+      qh[k] = (uint64_t)(uint32_t)(b[k] >> 32) * (uint32_t)(t[k].wb >> 32) + ((uint64_t)h1[k] + h2[k]);
 #pragma unroll
     for (int k = 0; k < NB; ++k) lo[k] = (uint64_t)(uint32_t)b[k] * (uint32_t)t[k].w + (uint64_t)(uint32_t)qh[k] * n0;
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
       const uint32_t b0 = (uint32_t)b[k], b1 = (uint32_t)(b[k] >> 32);
-      const uint32_t hi = (uint32_t)(lo[k] >> 32) + b0 * (uint32_t)(t[k].w >> 32) + b1 * (uint32_t)t[k].w +
-                          (uint32_t)qh[k] * n1 + (uint32_t)(qh[k] >> 32) * n0;
-      r[k] = make_u64((uint32_t)lo[k], hi);
+      const uint32_t cross = b0 * (uint32_t)(t[k].w >> 32) + b1 * (uint32_t)t[k].w + (uint32_t)qh[k] * n1 +
+                             (uint32_t)(qh[k] >> 32) * n0;
+      r[k] = make_u64((uint32_t)lo[k], add_u32((uint32_t)(lo[k] >> 32), cross));
     }
   }
   // Cooley-Tukey: X, Y in [0, 8q) -> X + WY, X - WY in [0, 8q).

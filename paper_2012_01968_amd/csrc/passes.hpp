@@ -49,17 +49,21 @@ struct PassArgs {
 
 // Base address and limb of vector `vec` of a launch: dense [P][L][N] batches place vector
 // p*L + l at data + (p*L + l)*N with prime l; list launches read both from the list.
+// Residue arrays live in device global memory; addressing them through this type lets
+// the compiler emit global (not flat) loads and stores.
+typedef __attribute__((address_space(1))) uint64_t gu64;
+
 struct VecRef {
-  uint64_t* base;
+  gu64* base;
   uint32_t limb;
 };
 
 __device__ __forceinline__ VecRef vec_ref(const PassArgs& a, uint64_t vec) {
   if (a.vecs) {
     const VecDesc d = a.vecs[vec];
-    return VecRef{d.ptr, d.limb};
+    return VecRef{(gu64*)d.ptr, d.limb};
   }
-  return VecRef{a.data + (vec << a.logN), (uint32_t)(vec % a.L)};
+  return VecRef{(gu64*)(a.data + (vec << a.logN)), (uint32_t)(vec % a.L)};
 }
 
 template <int Begin, int End, typename F>
