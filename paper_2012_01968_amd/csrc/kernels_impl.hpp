@@ -8,16 +8,26 @@
 namespace nttk {
 
 #ifndef NTTK_LR
-#define NTTK_LR 4
+#define NTTK_LR 3
 #endif
 constexpr int kLR = NTTK_LR;    // 2^kLR values per lane per register step
 #ifndef NTTK_COL_WIDTH
-#define NTTK_COL_WIDTH 8
+#define NTTK_COL_WIDTH 16
 #endif
 #ifndef NTTK_ROW_THREADS
 #define NTTK_ROW_THREADS 128
 #endif
+#ifndef NTTK_ROW_PRELOAD
+#define NTTK_ROW_PRELOAD 1
+#endif
 constexpr int kColWidth = NTTK_COL_WIDTH;     // columns per column-pass tile
+constexpr bool kRowPreload = NTTK_ROW_PRELOAD != 0;   // row pass: a step's twiddles loaded up front
+
+template <int R>
+struct PreTw {   // twiddles of one register step (see load_step_twiddles)
+  Tw w[R];
+  Tw w2[R];
+};
 constexpr int kRowThreads = NTTK_ROW_THREADS; // lanes per row-pass workgroup
 
 // Tile of this workgroup.  Workgroups are dispatched to the eight XCDs round-robin (block
@@ -97,6 +107,8 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void fwd_row_kernel(PassArgs a) {
 
   static_for<0, S::K>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
+    PreTw<S::R> pre;   // issued before the exchange so the loads overlap the barrier
+    if constexpr (kRowPreload) load_step_twiddles<LOGM, kLR, k, OTS>(pre.w, pre.w2, t, base, tabfn, ot);
     if constexpr (k > 0) {
 #pragma unroll
       for (int u = 0; u < S::R; ++u) l[lds_pad(S::template idx<k - 1>(t, u))] = x[u];
@@ -104,7 +116,8 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void fwd_row_kernel(PassArgs a) {
 #pragma unroll
       for (int u = 0; u < S::R; ++u) x[u] = l[lds_pad(S::template idx<k>(t, u))];
     }
-    ct_step<FAST, LOGM, kLR, k, OTS>(x, t, base, tabfn, ot, md);
+    if constexpr (kRowPreload) ct_step<FAST, LOGM, kLR, k, OTS>(x, t, base, tabfn, ot, md, pre);
+    else ct_step<FAST, LOGM, kLR, k, OTS>(x, t, base, tabfn, ot, md);
   });
 
 #pragma unroll
@@ -181,6 +194,8 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void inv_row_kernel(PassArgs a) {
 
   static_for_down<S::K, 0>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
+    PreTw<S::R> pre;   // issued before the exchange so the loads overlap the barrier
+    if constexpr (kRowPreload) load_step_twiddles<LOGM, kLR, k, OTS>(pre.w, pre.w2, t, base, tabfn, ot);
     if constexpr (k < S::K - 1) {
 #pragma unroll
       for (int u = 0; u < S::R; ++u) l[lds_pad(S::template idx<k + 1>(t, u))] = x[u];
@@ -188,7 +203,8 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void inv_row_kernel(PassArgs a) {
 #pragma unroll
       for (int u = 0; u < S::R; ++u) x[u] = l[lds_pad(S::template idx<k>(t, u))];
     }
-    gs_step<FAST, LOGM, kLR, k, OTS, SCALE0>(x, t, base, tabfn, ot, md, sc0, sc1);
+    if constexpr (kRowPreload) gs_step<FAST, LOGM, kLR, k, OTS, SCALE0>(x, t, base, tabfn, ot, md, sc0, sc1, pre);
+    else gs_step<FAST, LOGM, kLR, k, OTS, SCALE0>(x, t, base, tabfn, ot, md, sc0, sc1);
   });
 
   if constexpr (SCALE0) {
@@ -210,8 +226,8 @@ template <int LOGM>
 struct ColCfg {
   using S = Steps<LOGM, kLR>;
   static constexpr int M = 1 << LOGM;
-  static constexpr int W = kColWidth;
   static constexpr int T = M / S::R;      // lanes per column
+  static constexpr int W = kColWidth * T > 1024 ? 1024 / T : kColWidth;   // at most 1024 lanes
   static constexpr int NT = W * T;
   static constexpr int PITCH = W;         // LDS elements per matrix row
 };

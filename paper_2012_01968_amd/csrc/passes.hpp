@@ -112,12 +112,52 @@ struct OtTables {
   }
 };
 
+// The twiddles of one register step, loaded into registers before the step runs.
+// In stage bit (local index i = bit - blo) the twiddle of a butterfly depends only on the
+// lane's window bits above bit i, so the stage needs R >> (i + 1) distinct twiddles and
+// the whole step at most R - 1.  Slot of stage i, butterfly k (k-th index with bit i
+// clear): off(i) + (k >> i).  Loading them all up front costs one memory round trip per
+// step instead of one per stage.
+template <int LOGM, int LR, int K_STEP>
+struct StepSlots {
+  using S = Steps<LOGM, LR>;
+  static constexpr int lo = S::blo(K_STEP);
+  static constexpr int nb = S::nb(K_STEP);
+  static constexpr int R = S::R;
+  static constexpr int count(int i) { return R >> (i + 1); }
+  static constexpr int off(int i) { return R - (R >> i); }
+};
+
+struct NoTw {};   // stand-in for "no preloaded twiddles": gather them stage by stage
+
+template <int LOGM, int LR, int K_STEP, int OTS, int NR, typename TabFn>
+__device__ __forceinline__ void load_step_twiddles(Tw (&w)[NR], Tw (&w2)[NR], uint32_t t, uint32_t base,
+                                                   TabFn&& tab, const OtTables& ot) {
+  using SS = StepSlots<LOGM, LR, K_STEP>;
+  using S = typename SS::S;
+  static_assert(NR == S::R, "register array size");
+  static_for<SS::lo, SS::lo + SS::nb>([&](auto bit_c) {
+    constexpr int bit = decltype(bit_c)::value;
+    constexpr int s = LOGM - 1 - bit;
+    constexpr int i = bit - SS::lo;
+#pragma unroll
+    for (int j = 0; j < SS::count(i); ++j) {
+      const uint32_t r = S::template idx<K_STEP>(t, (uint32_t)(j << (i + 1)));
+      const uint32_t ix = (base << s) + (r >> (bit + 1));
+      if constexpr (OTS > 0 && s >= LOGM - OTS) ot.get(ix, w[SS::off(i) + j], w2[SS::off(i) + j]);
+      else w[SS::off(i) + j] = tab(ix);
+    }
+  });
+}
+
 // Forward (Cooley-Tukey) register step K_STEP on the R values of one lane.
 // TabFn(ix) returns the table twiddle Psi[ix]; the last OTS stages of this
 // sub-transform take their twiddles from `ot` instead.
-template <bool FAST, int LOGM, int LR, int K_STEP, int OTS, int NR, typename TabFn>
+// Pre: NoTw, or a struct with arrays w[R], w2[R] filled by load_step_twiddles.
+template <bool FAST, int LOGM, int LR, int K_STEP, int OTS, int NR, typename TabFn, typename Pre = NoTw>
 __device__ __forceinline__ void ct_step(uint64_t (&x)[NR], uint32_t t, uint32_t base,
-                                        TabFn&& tab, const OtTables& ot, const Mod& md) {
+                                        TabFn&& tab, const OtTables& ot, const Mod& md, const Pre& pre = Pre{}) {
+  constexpr bool PRE = !std::is_same<Pre, NoTw>::value;
   using A = Arith<FAST>;
   using S = Steps<LOGM, LR>;
   static_assert(NR == S::R, "register array size");
@@ -135,10 +175,16 @@ __device__ __forceinline__ void ct_step(uint64_t (&x)[NR], uint32_t t, uint32_t 
 #pragma unroll
       for (int k = 0; k < H; ++k) {
         const int u = ((k >> i) << (i + 1)) | (k & ((1 << i) - 1));   // k-th index with bit i clear
-        const uint32_t r = S::template idx<K_STEP>(t, (uint32_t)u);
-        const uint32_t ix = (base << s) + (r >> (bit + 1));
-        if constexpr (OTS > 0 && s >= LOGM - OTS) ot.get(ix, w[k], w2[k]);
-        else w[k] = tab(ix);
+        if constexpr (PRE) {
+          constexpr int o = StepSlots<LOGM, LR, K_STEP>::off(i);
+          w[k] = pre.w[o + (k >> i)];
+          if constexpr (OTS > 0 && s >= LOGM - OTS) w2[k] = pre.w2[o + (k >> i)];
+        } else {
+          const uint32_t r = S::template idx<K_STEP>(t, (uint32_t)u);
+          const uint32_t ix = (base << s) + (r >> (bit + 1));
+          if constexpr (OTS > 0 && s >= LOGM - OTS) ot.get(ix, w[k], w2[k]);
+          else w[k] = tab(ix);
+        }
         ys[k] = x[u | (1 << i)];
       }
 #pragma unroll
@@ -158,6 +204,13 @@ __device__ __forceinline__ void ct_step(uint64_t (&x)[NR], uint32_t t, uint32_t 
 #pragma unroll
       for (int u = 0; u < S::R; ++u) {
         if (u & (1 << i)) continue;
+        if constexpr (PRE) {
+          constexpr int o = StepSlots<LOGM, LR, K_STEP>::off(i);
+          if constexpr (OTS > 0 && s >= LOGM - OTS) A::ct2(x[u], x[u | (1 << i)], pre.w[o + (u >> (i + 1))],
+                                                           pre.w2[o + (u >> (i + 1))], md);
+          else A::ct(x[u], x[u | (1 << i)], pre.w[o + (u >> (i + 1))], md);
+          continue;
+        }
         const uint32_t r = S::template idx<K_STEP>(t, (uint32_t)u);
         const uint32_t ix = (base << s) + (r >> (bit + 1));
         if constexpr (OTS > 0 && s >= LOGM - OTS) {
@@ -176,10 +229,12 @@ __device__ __forceinline__ void ct_step(uint64_t (&x)[NR], uint32_t t, uint32_t 
 // Inverse (Gentleman-Sande) register step K_STEP: stages from the low bit up.
 // SCALE0: this sub-transform holds stage 0 of the whole transform, whose butterfly
 // also applies the 1/N scale (sc0 = 1/N, sc1 = Psi_inv[1]/N).
-template <bool FAST, int LOGM, int LR, int K_STEP, int OTS, bool SCALE0, int NR, typename TabFn>
+template <bool FAST, int LOGM, int LR, int K_STEP, int OTS, bool SCALE0, int NR, typename TabFn,
+          typename Pre = NoTw>
 __device__ __forceinline__ void gs_step(uint64_t (&x)[NR], uint32_t t, uint32_t base,
                                         TabFn&& tab, const OtTables& ot, const Mod& md,
-                                        const Tw& sc0, const Tw& sc1) {
+                                        const Tw& sc0, const Tw& sc1, const Pre& pre = Pre{}) {
+  constexpr bool PRE = !std::is_same<Pre, NoTw>::value;
   using A = Arith<FAST>;
   using S = Steps<LOGM, LR>;
   static_assert(NR == S::R, "register array size");
@@ -196,10 +251,16 @@ __device__ __forceinline__ void gs_step(uint64_t (&x)[NR], uint32_t t, uint32_t 
 #pragma unroll
       for (int k = 0; k < H; ++k) {
         const int u = ((k >> i) << (i + 1)) | (k & ((1 << i) - 1));
-        const uint32_t r = S::template idx<K_STEP>(t, (uint32_t)u);
-        const uint32_t ix = (base << s) + (r >> (bit + 1));
-        if constexpr (OTS > 0 && s >= LOGM - OTS) ot.get(ix, w[k], w2[k]);
-        else w[k] = tab(ix);
+        if constexpr (PRE) {
+          constexpr int o = StepSlots<LOGM, LR, K_STEP>::off(i);
+          w[k] = pre.w[o + (k >> i)];
+          if constexpr (OTS > 0 && s >= LOGM - OTS) w2[k] = pre.w2[o + (k >> i)];
+        } else {
+          const uint32_t r = S::template idx<K_STEP>(t, (uint32_t)u);
+          const uint32_t ix = (base << s) + (r >> (bit + 1));
+          if constexpr (OTS > 0 && s >= LOGM - OTS) ot.get(ix, w[k], w2[k]);
+          else w[k] = tab(ix);
+        }
       }
 #pragma unroll
       for (int k = 0; k < H; ++k) {
@@ -221,6 +282,11 @@ __device__ __forceinline__ void gs_step(uint64_t (&x)[NR], uint32_t t, uint32_t 
       if (u & (1 << i)) continue;
       if constexpr (SCALE0 && s == 0) {
         A::gs_scaled(x[u], x[u | (1 << i)], sc1, sc0, md);
+      } else if constexpr (PRE) {
+        constexpr int o = StepSlots<LOGM, LR, K_STEP>::off(i);
+        if constexpr (OTS > 0 && s >= LOGM - OTS) A::gs2(x[u], x[u | (1 << i)], pre.w[o + (u >> (i + 1))],
+                                                         pre.w2[o + (u >> (i + 1))], md);
+        else A::gs(x[u], x[u | (1 << i)], pre.w[o + (u >> (i + 1))], md);
       } else {
         const uint32_t r = S::template idx<K_STEP>(t, (uint32_t)u);
         const uint32_t ix = (base << s) + (r >> (bit + 1));
