@@ -40,6 +40,27 @@ def library_path() -> str:
 if not os.path.exists(_LIB_PATH):
     raise ImportError(f"{_LIB_PATH} is not built; run `python paper_2012_01968_amd/build.py`")
 
+
+def _share_torch_hip_runtime() -> None:
+    """Load PyTorch's own HIP runtime first, if PyTorch is installed, so that the library
+    binds to the same runtime as the tensors and streams it is handed.  PyTorch-ROCm ships
+    its own libamdhip64; if the library were loaded first it would bring in the system
+    copy, and a process with two HIP runtimes cannot pass device pointers between them."""
+    import importlib.util
+    try:
+        spec = importlib.util.find_spec("torch")
+    except (ImportError, ValueError):
+        return
+    if spec is None or not spec.submodule_search_locations:
+        return
+    for root in spec.submodule_search_locations:
+        path = os.path.join(root, "lib", "libamdhip64.so")
+        if os.path.exists(path):
+            ctypes.CDLL(path, mode=ctypes.RTLD_GLOBAL)
+            return
+
+
+_share_torch_hip_runtime()
 _lib = ctypes.CDLL(_LIB_PATH)
 
 

@@ -146,12 +146,13 @@ def tune(N: int, primes, polys: int = 1, *, steps: int = 20, warmup: int = 3, re
         return cache["entries"][key]
     x, bufs = _inputs(torch, N, primes, polys, 2 * MALL_BYTES)
     ref = None
-    tried, dropped = [], []
+    tried, dropped, refused = [], [], []
     t0 = time.perf_counter()
     for opts in candidates(N):
         try:
             plan = ntt_plan_create(N, primes, **opts)
-        except NttError:
+        except NttError as e:
+            refused.append({"opts": opts, "error": str(e)})
             continue
         try:
             y = x.clone()
@@ -170,7 +171,8 @@ def tune(N: int, primes, polys: int = 1, *, steps: int = 20, warmup: int = 3, re
         finally:
             plan.destroy()
     if not tried:
-        raise RuntimeError(f"no plan options work for N={N}")
+        first = refused[0]["error"] if refused else "every candidate disagreed with the first"
+        raise RuntimeError(f"no plan options work for N={N}: {first}")
     best = min(tried, key=lambda t: t["us"])
     entry = {"opts": best["opts"], "us": best["us"], "tried": sorted(tried, key=lambda t: t["us"]),
              "dropped": dropped, "seconds": round(time.perf_counter() - t0, 2)}

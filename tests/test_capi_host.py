@@ -103,3 +103,18 @@ def test_batch_argument_errors(lib):
     assert lib.ntt_batch_assign(None, None, 0, None) == -1
     assert lib.ntt_batch_run(None, 0, None) == -1
     assert lib.ntt_batch_destroy(None) == 0
+
+
+@pytest.mark.parametrize("order", ["package first", "torch first"])
+def test_one_hip_runtime_whatever_the_import_order(order):
+    """The binding and PyTorch must share one HIP runtime: a second libamdhip64 in the
+    process cannot use device pointers or streams of the first (plan creation then fails
+    with hipGetDevice errors)."""
+    import sys
+    pytest.importorskip("torch")
+    imports = "import paper_2012_01968_amd, torch" if order == "package first" else \
+        "import torch, paper_2012_01968_amd"
+    code = imports + "; print(len({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))"
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.strip() == "1"
