@@ -62,6 +62,57 @@ struct RowCfg {
 // Rows of length M = N / N1, V rows per workgroup; row g of the batch starts at
 // data + g*M, belongs to vector g / N1 and is row g mod N1 of that vector's matrix.
 
+// Read-only lookups that are the same for the whole workgroup (vector lists, primes) go
+// through the constant address space so that the compiler can use scalar loads.
+typedef const __attribute__((address_space(4))) VecDesc cVecDesc;
+typedef const __attribute__((address_space(4))) uint64_t cu64;
+
+struct RowRef {
+  gu64* rowp;      // start of this lane's row
+  uint32_t limb;   // its prime
+  uint32_t base;   // N1 + (row within its vector): the row's twiddle base
+  bool valid;      // false for padding rows
+};
+
+// Row v of this workgroup's tile.  When V divides N1 (every split launch with at least V
+// rows per vector) the tile's rows are consecutive rows of one vector, so the vector is
+// looked up once per workgroup; otherwise each row finds its own vector.
+template <typename C>
+__device__ __forceinline__ RowRef row_ref(const PassArgs& a, uint32_t v) {
+  const uint64_t rows = a.n_vec << a.logN1;
+  const uint32_t n_tiles = (uint32_t)((rows + C::V - 1) / C::V);
+  const uint32_t tile = __builtin_amdgcn_readfirstlane(xcd_tile(n_tiles));
+  const uint32_t N1 = 1u << a.logN1;
+  if ((uint32_t)C::V <= N1) {
+    const bool valid = tile < n_tiles;
+    const uint64_t h0 = valid ? (uint64_t)tile * C::V : 0;   // first row, limb-major order
+    const uint64_t lp = h0 >> a.logN1;
+    gu64* vb;
+    uint32_t limb;
+    if (a.vecs) {
+      const cVecDesc* d = (const cVecDesc*)a.vecs + lp;
+      vb = (gu64*)d->ptr;
+      limb = d->limb;
+    } else {
+      const uint64_t vec = a.logN1 ? limb_major_vec(lp, a.L, a.P) : lp;
+      vb = (gu64*)(a.data + (vec << a.logN));
+      limb = (uint32_t)(vec % a.L);
+    }
+    const uint32_t r = (uint32_t)(h0 & (N1 - 1)) + v;
+    return RowRef{vb + (size_t)r * C::M, limb, N1 + r, valid};
+  }
+  const uint64_t h = (uint64_t)tile * C::V + v;
+  const bool valid = tile < n_tiles && h < rows;
+  uint64_t g = 0;   // row index in [vector][row] order
+  if (valid) {
+    const uint64_t lp = h >> a.logN1;
+    g = ((a.vecs || !a.logN1 ? lp : limb_major_vec(lp, a.L, a.P)) << a.logN1) | (h & (N1 - 1));
+  }
+  const VecRef vr = vec_ref(a, g >> a.logN1);
+  const uint32_t r = (uint32_t)(g & (N1 - 1));
+  return RowRef{vr.base + (size_t)r * C::M, vr.limb, N1 + r, valid};
+}
+
 template <bool FAST, int LOGM, int OTS>
 __global__ __launch_bounds__(RowCfg<LOGM>::NT) void fwd_row_kernel(PassArgs a) {
   using A = Arith<FAST>;
@@ -69,21 +120,11 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void fwd_row_kernel(PassArgs a) {
   using S = typename C::S;
   __shared__ uint64_t lds[C::V * C::PITCH];
   const uint32_t tid = threadIdx.x, v = tid / C::T, t = tid % C::T;
-  const uint64_t rows = a.n_vec << a.logN1;
-  const uint32_t n_tiles = (uint32_t)((rows + C::V - 1) / C::V);
-  const uint32_t tile = xcd_tile(n_tiles);
-  const uint64_t h0 = (uint64_t)tile * C::V + v;   // row in limb-major order (natural when N1 = 1)
-  const bool valid = tile < n_tiles && h0 < rows;
-  const uint32_t N1 = 1u << a.logN1;
-  uint64_t g = 0;   // row index in [vector][row] order
-  if (valid) {
-    const uint64_t lp = h0 >> a.logN1;
-    g = ((a.vecs || !a.logN1 ? lp : limb_major_vec(lp, a.L, a.P)) << a.logN1) | (h0 & (N1 - 1));
-  }
-  const VecRef vr = vec_ref(a, g >> a.logN1);
-  const uint32_t limb = vr.limb;
-  const Mod md(a.q[limb]);
-  const uint32_t base = N1 + (uint32_t)(g & (N1 - 1));
+  const RowRef rr = row_ref<C>(a, v);
+  const bool valid = rr.valid;
+  const uint32_t limb = rr.limb;
+  const Mod md(((cu64*)a.q)[limb]);
+  const uint32_t base = rr.base;
   const Tw* tab = a.tw + ((size_t)limb << a.logN);
   OtTables ot{};
   if constexpr (OTS > 0) {
@@ -93,7 +134,7 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void fwd_row_kernel(PassArgs a) {
     ot.b = a.ot_log2_base;
   }
   auto tabfn = [&](uint32_t ix) { return tab[ix]; };
-  gu64* rowp = vr.base + (g & (N1 - 1)) * C::M;
+  gu64* rowp = rr.rowp;
   uint64_t* l = lds + v * C::PITCH;
 
   uint64_t x[S::R];
@@ -144,21 +185,11 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void inv_row_kernel(PassArgs a) {
   using S = typename C::S;
   __shared__ uint64_t lds[C::V * C::PITCH];
   const uint32_t tid = threadIdx.x, v = tid / C::T, t = tid % C::T;
-  const uint64_t rows = a.n_vec << a.logN1;
-  const uint32_t n_tiles = (uint32_t)((rows + C::V - 1) / C::V);
-  const uint32_t tile = xcd_tile(n_tiles);
-  const uint64_t h0 = (uint64_t)tile * C::V + v;   // row in limb-major order (natural when N1 = 1)
-  const bool valid = tile < n_tiles && h0 < rows;
-  const uint32_t N1 = 1u << a.logN1;
-  uint64_t g = 0;   // row index in [vector][row] order
-  if (valid) {
-    const uint64_t lp = h0 >> a.logN1;
-    g = ((a.vecs || !a.logN1 ? lp : limb_major_vec(lp, a.L, a.P)) << a.logN1) | (h0 & (N1 - 1));
-  }
-  const VecRef vr = vec_ref(a, g >> a.logN1);
-  const uint32_t limb = vr.limb;
-  const Mod md(a.q[limb]);
-  const uint32_t base = N1 + (uint32_t)(g & (N1 - 1));
+  const RowRef rr = row_ref<C>(a, v);
+  const bool valid = rr.valid;
+  const uint32_t limb = rr.limb;
+  const Mod md(((cu64*)a.q)[limb]);
+  const uint32_t base = rr.base;
   const Tw* tab = a.tw + ((size_t)limb << a.logN);
   OtTables ot{};
   if constexpr (OTS > 0) {
@@ -173,7 +204,7 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void inv_row_kernel(PassArgs a) {
     sc1 = a.scale[2 * limb + 1];
   }
   auto tabfn = [&](uint32_t ix) { return tab[ix]; };
-  gu64* rowp = vr.base + (g & (N1 - 1)) * C::M;
+  gu64* rowp = rr.rowp;
   uint64_t* l = lds + v * C::PITCH;
 
   uint64_t x[S::R];

@@ -19,8 +19,11 @@
 //                to less than 3 * 2^64, so the estimate undershoots the exact one by at
 //                most 2 and r lies in [0, 4q).  The low half is formed as
 //                b*w + qh*(2^64 - q) mod 2^64 with the four cross products folded into
-//                the high word.  Cooley-Tukey values live in [0, 8q), Gentleman-Sande
-//                values in [0, 4q); 8q < 2^63 lets the conditional subtraction test the
+//                the high word.  Gentleman-Sande values live in [0, 4q).  Cooley-Tukey
+//                values live in [0, 16q) (16q < 2^64): X is reduced by 8q only in every
+//                other stage, so a reducing stage maps inputs below 16q to outputs below
+//                12q and the plain stage after it maps those to outputs below 16q.  Every
+//                conditional subtraction has |x - m| < 8q < 2^63, so it can test the
 //                sign of x - m instead of comparing.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -33,9 +36,9 @@ struct Tw {  // a twiddle and its Shoup companion, stored as one 16-byte entry
 };
 
 struct Mod {  // per-prime constants
-  uint64_t q, q2, q4, nq, nq2, nq4;  // q, 2q, 4q, and their negatives mod 2^64
+  uint64_t q, q2, q4, nq, nq2, nq4, nq8;  // q, 2q, 4q, and the negatives mod 2^64 of q, 2q, 4q, 8q
   __device__ __forceinline__ explicit Mod(uint64_t p)
-      : q(p), q2(p << 1), q4(p << 2), nq(0 - p), nq2(0 - (p << 1)), nq4(0 - (p << 2)) {}
+      : q(p), q2(p << 1), q4(p << 2), nq(0 - p), nq2(0 - (p << 1)), nq4(0 - (p << 2)), nq8(0 - (p << 3)) {}
   Mod() = default;
 };
 
@@ -164,15 +167,18 @@ struct Arith<true> {
       r[k] = make_u64((uint32_t)lo[k], add_u32((uint32_t)(lo[k] >> 32), cross));
     }
   }
-  // Cooley-Tukey: X, Y in [0, 8q) -> X + WY, X - WY in [0, 8q).
+  // The kernels run this policy's butterflies stage by stage over all R/2 pairs of a lane
+  // (ct_step, gs_step in passes.hpp, on top of mul_n); the single-butterfly forms below
+  // keep the same ranges.
+  // Cooley-Tukey: X, Y in [0, 16q) -> X + WY, X - WY in [0, 12q).
   static __device__ __forceinline__ void ct(uint64_t& X, uint64_t& Y, const Tw& t, const Mod& m) {
-    const uint64_t x = csub_sign(X, m.nq4);
+    const uint64_t x = csub_sign(X, m.nq8);
     const uint64_t v = mul(Y, t, m);
     X = x + v;
     Y = x + m.q4 - v;
   }
   static __device__ __forceinline__ void ct2(uint64_t& X, uint64_t& Y, const Tw& a, const Tw& b, const Mod& m) {
-    const uint64_t x = csub_sign(X, m.nq4);
+    const uint64_t x = csub_sign(X, m.nq8);
     const uint64_t v = mul(mul(Y, a, m), b, m);
     X = x + v;
     Y = x + m.q4 - v;
@@ -190,6 +196,7 @@ struct Arith<true> {
     X = s;
     Y = mul(mul(d, a, m), b, m);
   }
+  // Stage 0 of a single-pass inverse, with the 1/N scale: X, Y in [0, 4q) -> [0, 4q).
   static __device__ __forceinline__ void gs_scaled(uint64_t& X, uint64_t& Y, const Tw& wn, const Tw& n,
                                                    const Mod& m) {
     const uint64_t s = X + Y;
@@ -197,8 +204,9 @@ struct Arith<true> {
     X = mul(s, n, m);
     Y = mul(d, wn, m);
   }
+  // [0, 16q) -> [0, q)
   static __device__ __forceinline__ uint64_t fwd_final(uint64_t x, const Mod& m) {
-    return csub_sign(csub_sign(csub_sign(x, m.nq4), m.nq2), m.nq);
+    return csub_sign(csub_sign(csub_sign(csub_sign(x, m.nq8), m.nq4), m.nq2), m.nq);
   }
   static __device__ __forceinline__ uint64_t inv_final(uint64_t x, const Mod& m) {
     return csub_sign(csub_sign(x, m.nq2), m.nq);

@@ -187,10 +187,12 @@ __device__ __forceinline__ void ct_step(uint64_t (&x)[NR], uint32_t t, uint32_t 
         }
         ys[k] = x[u | (1 << i)];
       }
+      // X is reduced by 8q in even stages only: values stay below 16q (see modarith.hpp)
+      constexpr bool reduce = (s % 2) == 0;
 #pragma unroll
       for (int k = 0; k < H; ++k) {
         const int u = ((k >> i) << (i + 1)) | (k & ((1 << i) - 1));
-        xs[k] = csub_sign(x[u], md.nq4);
+        xs[k] = reduce ? csub_sign(x[u], md.nq8) : x[u];
       }
       A::template mul_n<H>(v, ys, w, md);
       if constexpr (OTS > 0 && s >= LOGM - OTS) A::template mul_n<H>(v, v, w2, md);
