@@ -49,6 +49,24 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def variant_key(info: dict, ots: int) -> str:
+    """Name of a plan configuration, as used by the traffic summary."""
+    path = "fused" if info["kernel_path"] == 2 else "split"
+    return f"{'ot%d' % ots if ots else 'table'}-{path}-n1={info['log2_n1']}"
+
+
+def tune_shape(N: int, primes, polys: int) -> dict:
+    """The tuner's choice for one shape (measured now unless cached for this build)."""
+    from paper_2012_01968_amd import autotune
+    cached = autotune.lookup(N, primes, polys) is not None
+    t0 = time.perf_counter()
+    e = autotune.tune(N, primes, polys)
+    log(f"tuned N={N} L={len(primes)} P={polys}: {e['opts']} {e['us']:.1f} us "
+        f"({len(e['tried'])} candidates, {'cached' if cached else f'{time.perf_counter() - t0:.1f} s'})")
+    return {"opts": e["opts"], "us": e["us"], "candidates": len(e["tried"]), "cached": cached,
+            "seconds": round(time.perf_counter() - t0, 2)}
+
+
 def read_traffic(kernel: str, src_hash: str):
     """HBM bytes per launch from the committed counter summary, if it matches this source."""
     path = os.path.join(ROOT, "profiles", "traffic_counters.txt")
@@ -99,9 +117,11 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--variant", choices=["auto"] + list(VARIANTS), default="auto",
-                    help="auto measures every variant (table / OT twiddles x split / fused launch) and reports "
-                         "the fastest")
+    ap.add_argument("--variant", choices=["auto", "tuned"] + list(VARIANTS), default="auto",
+                    help="auto measures every named variant (table / OT twiddles x split / fused launch) and the "
+                         "tuner's choice, and reports the fastest")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the plan tuner: named variants only, default plans in the other sections")
     ap.add_argument("--log2-n1", type=int, default=0)
     ap.add_argument("--rotate-gib", type=float, default=1.25, help="total size of the rotating input copies")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -151,10 +171,17 @@ def main() -> int:
         log(f"profile run: {args.steps} steps ({mode}) + one {ct_bytes}-byte device copy")
         return 0
 
-    modes = list(VARIANTS) if args.variant == "auto" else [args.variant]
+    variants = dict(VARIANTS)
+    tuned = None
+    if args.variant in ("auto", "tuned") and not args.no_tune:
+        tuned = tune_shape(N, primes, P)
+        variants["tuned"] = tuned["opts"]
+    modes = list(variants) if args.variant == "auto" else [args.variant]
     results = {}
     for mode in modes:
-        plan = ntt.ntt_plan_create(N, primes, log2_n1=args.log2_n1, **VARIANTS[mode])
+        opts = dict(variants[mode])
+        opts.setdefault("log2_n1", args.log2_n1)
+        plan = ntt.ntt_plan_create(N, primes, **opts)
         info = ntt.ntt_plan_get_info(plan)
         npass = ntt.ntt_plan_num_passes(plan)
         fused = info["kernel_path"] == ntt.PATH_FUSED
@@ -229,7 +256,7 @@ def main() -> int:
     best = min(results, key=lambda m: results[m]["ms"])
     r = results[best]
     info = r["info"]
-    ots = info["ot_stages"] if best.startswith("ot") else 0
+    ots = info["ot_stages"] if info["twiddle_mode"] == ntt.TWIDDLE_OT else 0
     n_limb_ntts = 2 * P * L
     value = n_limb_ntts / (r["ms"] * 1e-3)
 
@@ -239,7 +266,7 @@ def main() -> int:
     alg_bytes = data_bytes(kind, N, L, P) + twiddle_bytes(kind, N, L, info["log2_n1"], ots)
     achieved = alg_bytes / (r["kms"][dom] * 1e-3) / 1e9
     src_hash = kernel_source_hash()
-    traffic = read_traffic(f"{best}:{dom}", src_hash)
+    traffic = read_traffic(f"{variant_key(info, ots)}:{dom}", src_hash)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "kernel_us": round(r["kms"][dom] * 1e3, 2), "alg_bytes_per_launch": alg_bytes}
@@ -264,8 +291,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": "one ciphertext, N=2^16, L=45 primes in [2^59,2^60) (seed 2), 2 polys, "
                                "forward NTT then inverse NTT (180 limb-NTTs per step)",
-                   "N": N, "L": L, "polys": P, "variant": best, "ot_stages": ots,
-                   "log2_n1": info["log2_n1"], "rotating_copies": R},
+                   "N": N, "L": L, "polys": P, "variant": best, "plan": variant_key(info, ots),
+                   "ot_stages": ots, "log2_n1": info["log2_n1"], "rotating_copies": R},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "step_hbm_frac": round(step_frac, 4),
@@ -275,6 +302,7 @@ def main() -> int:
         "kernel_us": {k: round(v * 1e3, 2) for k, v in r["kms"].items()},
         "modes_us_per_step": {m: round(results[m]["ms"] * 1e3, 2) for m in results},
         "roundtrip_ok": r["roundtrip_ok"],
+        "autotune": tuned,
         "uneven_batch": uneven,
         "serving": serving,
         "source_hash": src_hash,
@@ -301,7 +329,15 @@ def uneven_batch_bench(args):
     rng = np.random.default_rng(cfg["seed"])
     logNs = rng.choice(cfg["logNs"], size=cfg["polys"], p=cfg["weights"])
     Ls = rng.integers(cfg["L"][0], cfg["L"][1] + 1, size=cfg["polys"])
-    plans = {int(k): ntt.ntt_plan_create(1 << int(k), chain) for k in cfg["logNs"]}
+    plans, plan_names = {}, {}
+    for k in cfg["logNs"]:
+        k = int(k)
+        # the batch holds this many limb-vectors of size 2^k: tune for that many full polynomials
+        polys_k = max(1, -(-int(Ls[logNs == k].sum()) // Lmax))
+        opts = {} if args.no_tune else tune_shape(1 << k, chain, polys_k)["opts"]
+        plans[k] = ntt.ntt_plan_create(1 << k, chain, **opts)
+        info = ntt.ntt_plan_get_info(plans[k])
+        plan_names[k] = variant_key(info, info["ot_stages"] if info["twiddle_mode"] == ntt.TWIDDLE_OT else 0)
     src = {k: torch.from_numpy(synth.residue_batch(cfg["seed"] + k, chain, 1 << k, 1).view(np.int64)).to("cuda")
            .view(Lmax, 1 << k) for k in plans}
     jobs, bufs = [], []
@@ -315,7 +351,8 @@ def uneven_batch_bench(args):
     out = {"workload": f"{cfg['polys']} polys, N from 2^13..2^17 (weights {list(cfg['weights'])}), "
                        f"L uniform in [{cfg['L'][0]}, {cfg['L'][1]}], forward+inverse each (seed {cfg['seed']})",
            "limb_ntts_per_step": limb_ntts, "data_gib": round(data_gib, 3),
-           "polys_by_logN": {int(k): int((logNs == k).sum()) for k in cfg["logNs"]}}
+           "polys_by_logN": {int(k): int((logNs == k).sum()) for k in cfg["logNs"]},
+           "plans": plan_names}
     steps = max(5, min(args.steps, 40))
     for name, mode in (("plain", ntt.BATCH_PLAIN), ("grouped", ntt.BATCH_GROUPED), ("graph", ntt.BATCH_GRAPH)):
         for _ in range(3):
@@ -361,7 +398,7 @@ def serve_bench(args):
     plans, keys, src = {}, {}, {}
     for k in cfg["logNs"]:
         N = 1 << k
-        plans[N] = ntt.ntt_plan_create(N, chain)
+        plans[N] = ntt.ntt_plan_create(N, chain, **({} if args.no_tune else tune_shape(N, chain, cfg["polys"])["opts"]))
         key = torch.from_numpy(synth.residue_batch(cfg["seed"] * 100 + k, chain, N, 1).view(np.int64)).to("cuda")
         ntt.ntt_forward(plans[N], key)
         keys[N] = key.view(Lmax, N)

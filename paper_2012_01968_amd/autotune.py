@@ -30,7 +30,7 @@ import time
 from . import (PATH_FUSED, PATH_SPLIT, TWIDDLE_OT, TWIDDLE_TABLE, NttError, ntt_forward, ntt_inverse,
                ntt_plan_create, ntt_plan_get_info)
 
-__all__ = ["candidates", "source_hash", "cache_path", "tune", "plan_create_tuned"]
+__all__ = ["candidates", "source_hash", "cache_path", "lookup", "tune", "plan_create_tuned"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 FUSED_SHAPES = {(6, 7), (7, 7), (7, 8), (8, 8), (8, 9)}
@@ -132,6 +132,12 @@ def _time(torch, plan, bufs, steps: int, warmup: int) -> float:
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) * 1e3 / steps
+
+
+def lookup(N: int, primes, polys: int = 1, path: str | None = None):
+    """The cached entry for this shape on this device and kernel build, or None."""
+    import torch
+    return _load(path or cache_path())["entries"].get(_key(_device_name(torch), N, primes, polys))
 
 
 def tune(N: int, primes, polys: int = 1, *, steps: int = 20, warmup: int = 3, refresh: bool = False,
