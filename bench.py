@@ -49,6 +49,18 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def ramp(step, ms: float) -> None:
+    """Run step(i) until at least `ms` of wall time has passed (GPU clock ramp-up)."""
+    import torch
+    t0 = time.perf_counter()
+    i = 0
+    while (time.perf_counter() - t0) * 1e3 < ms:
+        for _ in range(8):
+            step(i)
+            i += 1
+        torch.cuda.synchronize()
+
+
 def variant_key(info: dict, ots: int) -> str:
     """Name of a plan configuration, as used by the traffic summary."""
     path = "fused" if info["kernel_path"] == 2 else "split"
@@ -67,9 +79,9 @@ def tune_shape(N: int, primes, polys: int) -> dict:
             "seconds": round(time.perf_counter() - t0, 2)}
 
 
-def read_traffic(kernel: str, src_hash: str):
+def read_traffic(kernel: str, src_hash: str, path: str | None = None):
     """HBM bytes per launch from the committed counter summary, if it matches this source."""
-    path = os.path.join(ROOT, "profiles", "traffic_counters.txt")
+    path = path or os.path.join(ROOT, "profiles", "traffic_counters.txt")
     if not os.path.exists(path):
         return None
     rec = {}
@@ -77,7 +89,7 @@ def read_traffic(kernel: str, src_hash: str):
         line = line.strip()
         if not line or line.startswith("#") or ":" not in line:
             continue
-        k, v = line.split(":", 1)
+        k, _, v = line.rpartition(":")   # keys may hold ':' themselves
         rec[k.strip()] = v.strip()
     if rec.get("source_hash") != src_hash:
         return None
@@ -116,7 +128,10 @@ def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--ramp-ms", type=float, default=50.0,
+                    help="before the warmup steps, run steps for at least this long: the GPU's clocks rise "
+                         "over tens of milliseconds, and a cold start would be timed otherwise")
     ap.add_argument("--variant", choices=["auto", "tuned"] + list(VARIANTS), default="auto",
                     help="auto measures every named variant (table / OT twiddles x split / fused launch) and the "
                          "tuner's choice, and reports the fastest")
@@ -191,20 +206,29 @@ def main() -> int:
             ntt.ntt_forward(plan, b)
             ntt.ntt_inverse(plan, b)
 
+        ramp(step, args.ramp_ms)
         for i in range(args.warmup):
             step(i)
         torch.cuda.synchronize()
-        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        # the timed steps: events only around the whole run (an event between steps makes the
+        # queue drain before the next kernel starts, which would be timed as well)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
-        evs[0].record()
+        e0.record()
         for i in range(args.steps):
             step(args.warmup + i)
-            evs[i + 1].record()
+        e1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        ms = e0.elapsed_time(e1) / args.steps
+        # per-step latency distribution: a second pass with an event after every step
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        evs[0].record()
+        for i in range(args.steps):
+            step(i)
+            evs[i + 1].record()
+        torch.cuda.synchronize()
         per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
-        total_ms = evs[0].elapsed_time(evs[-1])
-        ms = total_ms / args.steps
 
         # per-kernel durations: the same steps with an event between consecutive kernels
         if fused:
@@ -355,9 +379,17 @@ def uneven_batch_bench(args):
            "plans": plan_names}
     steps = max(5, min(args.steps, 40))
     for name, mode in (("plain", ntt.BATCH_PLAIN), ("grouped", ntt.BATCH_GROUPED), ("graph", ntt.BATCH_GRAPH)):
+        ramp(lambda i: ntt.ntt_batch_run(batch, mode), args.ramp_ms)
         for _ in range(3):
             ntt.ntt_batch_run(batch, mode)
         torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for i in range(steps):
+            ntt.ntt_batch_run(batch, mode)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
         evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
         evs[0].record()
         for i in range(steps):
@@ -365,7 +397,6 @@ def uneven_batch_bench(args):
             evs[i + 1].record()
         torch.cuda.synchronize()
         per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(steps)])
-        ms = evs[0].elapsed_time(evs[-1]) / steps
         out[name] = {"ms_per_step": round(ms, 4), "limb_ntts_per_s": round(limb_ntts / (ms * 1e-3), 1),
                      "p50_ms": round(float(np.percentile(per, 50)), 4),
                      "p99_ms": round(float(np.percentile(per, 99)), 4)}

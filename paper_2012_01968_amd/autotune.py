@@ -118,11 +118,18 @@ def _inputs(torch, N: int, primes, polys: int, rotate_bytes: int):
     return x, bufs
 
 
-def _time(torch, plan, bufs, steps: int, warmup: int) -> float:
+def _time(torch, plan, bufs, steps: int, warmup: int, ramp_s: float = 0.01) -> float:
     R = bufs.shape[0]
-    for i in range(warmup):
+    t0 = time.perf_counter()
+    i = 0
+    # at least `warmup` round trips and `ramp_s` seconds, so that every candidate is timed at
+    # the same (risen) clock
+    while i < warmup or time.perf_counter() - t0 < ramp_s:
         ntt_forward(plan, bufs[i % R])
         ntt_inverse(plan, bufs[i % R])
+        i += 1
+        if i % 8 == 0:
+            torch.cuda.synchronize()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -140,7 +147,7 @@ def lookup(N: int, primes, polys: int = 1, path: str | None = None):
     return _load(path or cache_path())["entries"].get(_key(_device_name(torch), N, primes, polys))
 
 
-def tune(N: int, primes, polys: int = 1, *, steps: int = 20, warmup: int = 3, refresh: bool = False,
+def tune(N: int, primes, polys: int = 1, *, steps: int = 100, warmup: int = 3, refresh: bool = False,
          path: str | None = None, log=None) -> dict:
     """Best option set for (N, primes, polys); measured unless cached.  Returns
     {"opts": {...}, "us": forward+inverse microseconds per call, "tried": [...]}."""

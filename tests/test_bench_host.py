@@ -1,0 +1,38 @@
+"""Host helpers of bench.py (no GPU): the traffic summary lookup and the plan names."""
+import importlib.util
+import os
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def load_bench():
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_traffic_lookup(tmp_path):
+    b = load_bench()
+    f = tmp_path / "t.txt"
+    f.write_text("# comment\nsource_hash: abc\nbytes_per_launch[table-split-n1=8:fwd_row]: 146540105\n")
+    assert b.read_traffic("table-split-n1=8:fwd_row", "abc", str(f)) == 146540105.0
+    assert b.read_traffic("table-split-n1=8:inv_row", "abc", str(f)) is None
+    assert b.read_traffic("table-split-n1=8:fwd_row", "other", str(f)) is None   # stale counters
+
+
+def test_committed_traffic_covers_its_configuration():
+    b = load_bench()
+    path = os.path.join(ROOT, "profiles", "traffic_counters.txt")
+    text = open(path).read()
+    h = [l.split(":", 1)[1].strip() for l in text.splitlines() if l.startswith("source_hash")][0]
+    keys = [l.split("]")[0].split("[", 1)[1] for l in text.splitlines() if l.startswith("bytes_per_launch[")]
+    assert keys
+    for k in keys:
+        assert b.read_traffic(k, h) > 0
+
+
+def test_plan_names():
+    b = load_bench()
+    assert b.variant_key({"kernel_path": 1, "log2_n1": 8}, 0) == "table-split-n1=8"
+    assert b.variant_key({"kernel_path": 2, "log2_n1": 7}, 2) == "ot2-fused-n1=7"
