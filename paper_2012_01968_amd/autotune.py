@@ -84,8 +84,11 @@ def _key(device: str, N: int, primes, polys: int) -> str:
 
 
 def _device_name(torch) -> str:
+    """Architecture and compute-unit count: what the measured choice depends on (the
+    marketing name string differs between otherwise identical boxes)."""
     p = torch.cuda.get_device_properties(torch.cuda.current_device())
-    return f"{p.name}:{getattr(p, 'gcnArchName', '')}"
+    arch = (getattr(p, "gcnArchName", "") or p.name).split(":")[0]
+    return f"{arch}:{p.multi_processor_count}CU"
 
 
 def _load(path: str) -> dict:

@@ -43,7 +43,7 @@ def test_cache_round_trip(tmp_path):
     p = str(tmp_path / "cache.json")
     assert at._load(p) == {"version": 1, "entries": {}}
     cache = at._load(p)
-    key = at._key("dev:gfx950", 1 << 16, [(1 << 59) + 1, (1 << 58) + 1], 2)
+    key = at._key("gfx950:256CU", 1 << 16, [(1 << 59) + 1, (1 << 58) + 1], 2)
     assert key.endswith("|N=65536|L=2|P=2|qbits=60") and at.source_hash() in key
     cache["entries"][key] = {"opts": {"log2_n1": 8, "kernel_path": PATH_SPLIT, "twiddle_mode": TWIDDLE_TABLE},
                              "us": 1.0}
