@@ -1,0 +1,84 @@
+// Range claims of the fast arithmetic policy (primes below 2^60), checked on the host with
+// unsigned __int128 as the reference.  The product below restates the kernels' formula: the
+// Shoup quotient estimated from the three high 32x32 partial products of b * wb, and the
+// remainder b*w - qh*q taken modulo 2^64.
+//   1. for any b < 2^64 the remainder lies in [0, 4q) and is congruent to b*w mod q;
+//   2. Cooley-Tukey butterflies that reduce X by 8q only in even stages keep values below 16q,
+//      and every conditional subtraction has |x - m| < 2^63 (the sign test is valid);
+//   3. the forward final reduction (8q, 4q, 2q, q) maps [0, 16q) onto [0, q).
+#include <cstdint>
+#include <cstdio>
+#include <random>
+
+typedef unsigned __int128 u128;
+
+static uint64_t mulmod(uint64_t a, uint64_t b, uint64_t q) { return (uint64_t)((u128)a * b % q); }
+
+static uint64_t fast_mul(uint64_t b, uint64_t w, uint64_t wb, uint64_t q) {
+  const uint64_t b0 = (uint32_t)b, b1 = b >> 32, s0 = (uint32_t)wb, s1 = wb >> 32;
+  const uint64_t h1 = (b0 * s1) >> 32, h2 = (b1 * s0) >> 32;
+  const uint64_t qh = b1 * s1 + h1 + h2;   // < 2^64: it is at most floor(b * wb / 2^64)
+  return b * w - qh * q;                   // modulo 2^64
+}
+
+static long failures = 0;
+static void fail(const char* what, uint64_t q, uint64_t a, uint64_t b) {
+  if (failures++ < 10) std::printf("FAIL %s q=%llu a=%llu b=%llu\n", what, (unsigned long long)q,
+                                   (unsigned long long)a, (unsigned long long)b);
+}
+
+// conditional subtraction by the sign of x - m; records whether the sign test was valid
+static uint64_t csub(uint64_t x, uint64_t m, uint64_t q) {
+  const u128 diff = x >= m ? (u128)(x - m) : (u128)(m - x);
+  if (diff >= ((u128)1 << 63)) fail("|x - m| >= 2^63", q, x, m);
+  const uint64_t d = x - m;
+  return (int64_t)d < 0 ? x : d;
+}
+
+int main() {
+  std::mt19937_64 g(2012);
+  for (int trial = 0; trial < 300000; ++trial) {
+    const int bits = 30 + (int)(g() % 31);   // 30..60-bit odd moduli (primality is irrelevant here)
+    uint64_t q = (g() >> (64 - bits)) | (1ull << (bits - 1)) | 1;
+    if (q >= (1ull << 60)) q = (1ull << 60) - 1;
+    const uint64_t w = g() % q, wb = (uint64_t)(((u128)w << 64) / q);
+    uint64_t b;
+    switch (trial % 5) {
+      case 0: b = g(); break;
+      case 1: b = g() % (16 * q); break;
+      case 2: b = ~0ull - (g() & 0xffff); break;
+      case 3: b = 16 * q - 1 - (g() & 7); break;
+      default: b = g() & 0xff;
+    }
+    const uint64_t r = fast_mul(b, w, wb, q);
+    if (r >= 4 * q) fail("product >= 4q", q, b, w);
+    if (r % q != mulmod(b % q, w % q, q)) fail("product not congruent", q, b, w);
+  }
+  // butterfly ranges: run random stage sequences with values pushed to the top of each range
+  for (int trial = 0; trial < 20000; ++trial) {
+    const int bits = 40 + (int)(g() % 21);
+    uint64_t q = (g() >> (64 - bits)) | (1ull << (bits - 1)) | 1;
+    if (q >= (1ull << 60)) q = (1ull << 60) - 1;
+    uint64_t X = g() % q, Y = g() % q;   // canonical input
+    const uint64_t X0 = X, Y0 = Y;
+    uint64_t xr = X0 % q, yr = Y0 % q;   // reference residues of the same two values
+    const int stages = 1 + (int)(g() % 17);
+    for (int s = 0; s < stages; ++s) {
+      const uint64_t w = g() % q, wb = (uint64_t)(((u128)w << 64) / q);
+      const uint64_t x = (s % 2 == 0) ? csub(X, 8 * q, q) : X;
+      const uint64_t t = fast_mul(Y, w, wb, q);
+      const uint64_t nx = x + t, ny = x + 4 * q - t;
+      if (nx >= 16 * q || ny >= 16 * q) fail("butterfly output >= 16q", q, nx, ny);
+      const uint64_t rt = mulmod(yr, w, q);
+      const uint64_t rx = (xr + rt) % q, ry = (xr + q - rt) % q;
+      if (nx % q != rx || ny % q != ry) fail("butterfly not congruent", q, nx, ny);
+      // keep the larger output on the X side so the worst case propagates
+      if (g() & 1) { X = nx; Y = ny; xr = rx; yr = ry; } else { X = ny; Y = nx; xr = ry; yr = rx; }
+    }
+    uint64_t v = X;
+    v = csub(v, 8 * q, q); v = csub(v, 4 * q, q); v = csub(v, 2 * q, q); v = csub(v, q, q);
+    if (v >= q || v != xr) fail("final reduction", q, X, v);
+  }
+  std::printf("%ld failures\n", failures);
+  return failures != 0;
+}
