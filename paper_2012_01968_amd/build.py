@@ -17,6 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.environ.get("NTT_BUILD_DIR") or os.path.join(ROOT, "_build", "ntt")
 LIB = os.environ.get("NTT_BUILD_OUT") or os.path.join(HERE, "libntt_mi355x.so")
 SOURCES = ["kernels_fwd_fast.hip", "kernels_inv_fast.hip", "kernels_fwd_wide.hip", "kernels_inv_wide.hip",
+           "kernels_mul_fast.hip", "kernels_mul_wide.hip",
            "fused_fwd.hip", "fused_inv.hip", "kernels.hip", "capi.cpp"]
 ARCH = os.environ.get("NTT_OFFLOAD_ARCH", "gfx950")
 

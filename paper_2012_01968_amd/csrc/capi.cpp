@@ -130,6 +130,8 @@ struct ntt_plan_s {
     a.logN1 = logN1;
     a.ot_log2_base = ot_log2_base;
     a.fast = fast ? 1u : 0u;
+    a.mu = d_mu;
+    a.bits = d_bits;
     return a;
   }
   int active_ot() const { return twiddle_mode == NTT_TWIDDLE_OT ? ot_stages : 0; }
@@ -329,8 +331,8 @@ static ntt_status check_data(ntt_plan_t plan, const void* ptr, uint32_t n_polys)
 struct ntt_batch_s {
   struct Group {                        // every vector of the jobs that share one plan
     ntt_plan_t plan = nullptr;
-    uint64_t off_fwd = 0, off_key = 0, off_inv = 0;   // positions in the descriptor arena
-    uint64_t n_fwd = 0, n_key = 0, n_inv = 0;
+    uint64_t off_fwd = 0, off_key = 0, off_inv = 0, off_full = 0;   // positions in the descriptor arena
+    uint64_t n_fwd = 0, n_key = 0, n_inv = 0, n_full = 0;
   };
   std::vector<ntt_job> jobs;
   std::vector<Group> groups;
@@ -368,26 +370,48 @@ struct ntt_batch_s {
 
   // Enqueue the grouped work: all forward vector lists, then the key products, then all
   // inverse lists.
+  PassArgs list_args(const Group& g, uint64_t off, uint64_t n, bool inverse) const {
+    PassArgs a = g.plan->args(nullptr, 1, inverse);
+    a.vecs = at(off);
+    a.n_vec = n;
+    a.P = 1;
+    a.L = g.plan->L;
+    return a;
+  }
+
+  // Enqueue the grouped work in three phases over all plans: forward transforms, then key
+  // products, then inverse transforms.  Vectors of jobs that do all three ("full") take the
+  // forward column pass in phase 0, the row passes with the key product (one launch) in
+  // phase 1 and the inverse column pass in phase 2; a single-pass size does it all in phase 1.
   hipError_t grouped(hipStream_t st) const {
     for (int phase = 0; phase < 3; ++phase) {
       for (const Group& g : groups) {
+        const int ot = g.plan->active_ot();
+        const bool split = g.plan->logN1 != 0;
+        hipError_t e = hipSuccess;
         if (phase == 1) {
-          if (!g.n_key) continue;
-          const hipError_t e = nttk::launch_pointwise_list(at(g.off_key), g.n_key, g.plan->logN, g.plan->d_q,
-                                                           g.plan->d_mu, g.plan->d_bits, st);
-          if (e != hipSuccess) return e;
+          if (g.n_key &&
+              (e = nttk::launch_pointwise_list(at(g.off_key), g.n_key, g.plan->logN, g.plan->d_q, g.plan->d_mu,
+                                               g.plan->d_bits, st)) != hipSuccess)
+            return e;
+          if (g.n_full &&
+              (e = nttk::launch_mul_rows(list_args(g, g.off_full, g.n_full, false),
+                                         list_args(g, g.off_full, g.n_full, true), ot, st)) != hipSuccess)
+            return e;
           continue;
         }
-        const uint64_t n = phase ? g.n_inv : g.n_fwd;
-        if (!n) continue;
-        PassArgs a = g.plan->args(nullptr, 1, phase == 2);
-        a.vecs = at(phase ? g.off_inv : g.off_fwd);
-        a.n_vec = n;
-        a.P = 1;
-        a.L = g.plan->L;
-        const hipError_t e = phase ? nttk::launch_inverse(a, g.plan->active_ot(), st)
-                                   : nttk::launch_forward(a, g.plan->active_ot(), st);
-        if (e != hipSuccess) return e;
+        const bool inv = phase == 2;
+        const uint64_t n = inv ? g.n_inv : g.n_fwd;
+        if (n) {
+          const PassArgs a = list_args(g, inv ? g.off_inv : g.off_fwd, n, inv);
+          if ((e = inv ? nttk::launch_inverse(a, ot, st) : nttk::launch_forward(a, ot, st)) != hipSuccess) return e;
+        }
+        if (g.n_full && split) {
+          const PassArgs a = list_args(g, g.off_full, g.n_full, inv);
+          if ((e = inv ? nttk::launch_inverse_pass(a, ot, 1, st) : nttk::launch_forward_pass(a, ot, 0, st)) !=
+              hipSuccess)
+            return e;
+        }
       }
     }
     return hipSuccess;
@@ -417,7 +441,7 @@ static ntt_status plan_batch(ntt_batch_s* b, const ntt_job* jobs, uint32_t n_job
   for (ntt_plan_t plan : plans) {
     ntt_batch_s::Group g;
     g.plan = plan;
-    std::vector<nttk::VecDesc> fwd, key, inv;
+    std::vector<nttk::VecDesc> fwd, key, inv, full;
     // limb-major: the polynomials of one limb are adjacent, so launches meet its twiddles together
     for (uint32_t l = 0; l < plan->L; ++l) {
       for (const ntt_job& job : js) {
@@ -426,16 +450,18 @@ static ntt_status plan_batch(ntt_batch_s* b, const ntt_job* jobs, uint32_t n_job
         if (l >= lim) continue;
         for (uint32_t p = 0; p < job.n_polys; ++p) {
           nttk::VecDesc d{job.d_data + ((uint64_t)p * lim + l) * plan->N, nullptr, l, 0};
+          if (job.op & NTT_OP_MULKEY) d.key = job.d_key + (uint64_t)l * plan->N;
+          if (job.op == (NTT_OP_FORWARD | NTT_OP_MULKEY | NTT_OP_INVERSE)) {
+            full.push_back(d);
+            continue;
+          }
           if (job.op & NTT_OP_FORWARD) fwd.push_back(d);
           if (job.op & NTT_OP_INVERSE) inv.push_back(d);
-          if (job.op & NTT_OP_MULKEY) {
-            d.key = job.d_key + (uint64_t)l * plan->N;
-            key.push_back(d);
-          }
+          if (job.op & NTT_OP_MULKEY) key.push_back(d);
         }
       }
     }
-    for (auto* list : {&fwd, &key, &inv})
+    for (auto* list : {&fwd, &key, &inv, &full})
       if (list->size() * ((uint64_t)plan->N / 16 + 1) >= (1ull << 31)) return fail(NTT_ERR_ARG, "batch too large for one launch");
     g.off_fwd = desc.size();
     g.n_fwd = fwd.size();
@@ -446,6 +472,9 @@ static ntt_status plan_batch(ntt_batch_s* b, const ntt_job* jobs, uint32_t n_job
     g.off_inv = desc.size();
     g.n_inv = inv.size();
     desc.insert(desc.end(), inv.begin(), inv.end());
+    g.off_full = desc.size();
+    g.n_full = full.size();
+    desc.insert(desc.end(), full.begin(), full.end());
     groups.push_back(g);
   }
   b->jobs.swap(js);
@@ -650,18 +679,46 @@ ntt_status ntt_polymul_negacyclic(ntt_plan_t plan, const uint64_t* d_a, const ui
     if (plan->scratch_pending && (e = hipStreamWaitEvent(st, plan->scratch_ev, 0)) != hipSuccess)
       return hip_fail(e, "ordering scratch use");
     uint64_t* tmp = plan->scratch;
-    if (d_c != d_a && (e = hipMemcpyAsync(d_c, d_a, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess)
-      return hip_fail(e, "copying a");
-    if ((e = hipMemcpyAsync(tmp, d_b, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess)
-      return hip_fail(e, "copying b");
     const int ot = plan->active_ot();
-    (void)ot;
-    if ((e = transform(plan, d_c, n_polys, false, st)) != hipSuccess ||
-        (e = transform(plan, tmp, n_polys, false, st)) != hipSuccess ||
-        (e = nttk::launch_pointwise(d_c, tmp, d_c, plan->d_q, plan->d_mu, plan->d_bits,
-                                    (uint64_t)n_polys * plan->L * plan->N, plan->logN, plan->L, st)) != hipSuccess ||
-        (e = transform(plan, d_c, n_polys, true, st)) != hipSuccess)
-      return hip_fail(e, "ntt_polymul_negacyclic launch");
+    if (plan->kernel_path == NTT_PATH_SPLIT) {
+      // NTT(b) into the scratch (first pass out of place), then a: its forward column pass
+      // out of place into c, the row passes with the product by NTT(b) in one launch, and
+      // the inverse column pass.  A single-pass size does the whole product in that launch.
+      PassArgs fb = plan->args(tmp, n_polys, false);
+      PassArgs fa = plan->args(d_c, n_polys, false);
+      const PassArgs ia = plan->args(d_c, n_polys, true);
+      fb.src = d_b;
+      fa.src = d_a;
+      fa.key = tmp;
+      if (plan->logN1) {
+        PassArgs fa_col = fa;
+        fa_col.key = nullptr;
+        fa.src = nullptr;   // the row launch reads c, which the column pass wrote
+        PassArgs fb_row = fb;
+        fb_row.src = nullptr;
+        if ((e = nttk::launch_forward_pass(fb, ot, 0, st)) != hipSuccess ||
+            (e = nttk::launch_forward_pass(fb_row, ot, 1, st)) != hipSuccess ||
+            (e = nttk::launch_forward_pass(fa_col, ot, 0, st)) != hipSuccess ||
+            (e = nttk::launch_mul_rows(fa, ia, ot, st)) != hipSuccess ||
+            (e = nttk::launch_inverse_pass(ia, ot, 1, st)) != hipSuccess)
+          return hip_fail(e, "ntt_polymul_negacyclic launch");
+      } else if ((e = nttk::launch_forward_pass(fb, ot, 0, st)) != hipSuccess ||
+                 (e = nttk::launch_mul_rows(fa, ia, ot, st)) != hipSuccess) {
+        return hip_fail(e, "ntt_polymul_negacyclic launch");
+      }
+    } else {
+      if (d_c != d_a && (e = hipMemcpyAsync(d_c, d_a, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+        return hip_fail(e, "copying a");
+      if ((e = hipMemcpyAsync(tmp, d_b, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+        return hip_fail(e, "copying b");
+      if ((e = transform(plan, d_c, n_polys, false, st)) != hipSuccess ||
+          (e = transform(plan, tmp, n_polys, false, st)) != hipSuccess ||
+          (e = nttk::launch_pointwise(d_c, tmp, d_c, plan->d_q, plan->d_mu, plan->d_bits,
+                                      (uint64_t)n_polys * plan->L * plan->N, plan->logN, plan->L, st)) !=
+              hipSuccess ||
+          (e = transform(plan, d_c, n_polys, true, st)) != hipSuccess)
+        return hip_fail(e, "ntt_polymul_negacyclic launch");
+    }
     if ((e = hipEventRecord(plan->scratch_ev, st)) != hipSuccess) return hip_fail(e, "recording scratch event");
     plan->scratch_pending = true;
     return NTT_OK;

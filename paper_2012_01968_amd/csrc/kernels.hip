@@ -9,10 +9,14 @@ template <bool FAST>
 hipError_t forward_pass(const PassArgs& a, int ots, int pass, hipStream_t st);
 template <bool FAST>
 hipError_t inverse_pass(const PassArgs& a, int ots, int pass, hipStream_t st);
+template <bool FAST>
+hipError_t mul_rows(const PassArgs& af, const PassArgs& ai, int ots, hipStream_t st);
 extern template hipError_t forward_pass<true>(const PassArgs&, int, int, hipStream_t);
 extern template hipError_t forward_pass<false>(const PassArgs&, int, int, hipStream_t);
 extern template hipError_t inverse_pass<true>(const PassArgs&, int, int, hipStream_t);
 extern template hipError_t inverse_pass<false>(const PassArgs&, int, int, hipStream_t);
+extern template hipError_t mul_rows<true>(const PassArgs&, const PassArgs&, int, hipStream_t);
+extern template hipError_t mul_rows<false>(const PassArgs&, const PassArgs&, int, hipStream_t);
 
 // ------------------------------------------------------------------------ element-wise
 // c = a * b mod q_l over a [n_vec][N] batch, two elements per lane per iteration.
@@ -78,6 +82,11 @@ hipError_t launch_forward_pass(const PassArgs& a, int ots, int pass, hipStream_t
 hipError_t launch_inverse_pass(const PassArgs& a, int ots, int pass, hipStream_t st) {
   if (!shape_supported(a.logN, a.logN1, ots)) return hipErrorInvalidValue;
   return a.fast ? inverse_pass<true>(a, ots, pass, st) : inverse_pass<false>(a, ots, pass, st);
+}
+
+hipError_t launch_mul_rows(const PassArgs& af, const PassArgs& ai, int ots, hipStream_t st) {
+  if (!shape_supported(af.logN, af.logN1, ots)) return hipErrorInvalidValue;
+  return af.fast ? mul_rows<true>(af, ai, ots, st) : mul_rows<false>(af, ai, ots, st);
 }
 
 hipError_t launch_forward(const PassArgs& a, int ots, hipStream_t st) {

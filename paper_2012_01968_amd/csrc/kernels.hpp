@@ -20,6 +20,12 @@ hipError_t launch_inverse(const PassArgs& a, int ot_stages, hipStream_t st);
 hipError_t launch_forward_pass(const PassArgs& a, int ot_stages, int pass, hipStream_t st);
 hipError_t launch_inverse_pass(const PassArgs& a, int ot_stages, int pass, hipStream_t st);
 
+// Row passes of a product with an NTT-domain key (forward row stages, key product, inverse
+// row stages in one launch); `af` holds the forward tables and the keys, `ai` the inverse
+// tables.  With logN1 = 0 this is the whole product; otherwise the forward column pass
+// comes before it and the inverse column pass after it.
+hipError_t launch_mul_rows(const PassArgs& af, const PassArgs& ai, int ot_stages, hipStream_t st);
+
 // Fused single-launch transform (both passes, XCD-local queues); see fused.hpp.
 struct FusedArgs;
 bool fused_supported(uint32_t logN, uint32_t logN1, int ot_stages);

@@ -10,7 +10,15 @@ namespace nttk {
 #ifndef NTTK_LR
 #define NTTK_LR 3
 #endif
-constexpr int kLR = NTTK_LR;    // 2^kLR values per lane per register step
+#ifndef NTTK_ROW_LR
+#define NTTK_ROW_LR 0
+#endif
+constexpr int kLR = NTTK_LR;    // 2^kLR values per lane per register step (column pass)
+// Row pass: NTTK_ROW_LR if set, else kLR; policy 9 takes 16 values per lane for rows of at
+// least 2^10 points and kLR below.
+constexpr int row_lr(int logm) {
+  return NTTK_ROW_LR == 9 ? (logm >= 10 ? 4 : kLR) : (NTTK_ROW_LR > 0 ? NTTK_ROW_LR : kLR);
+}
 #ifndef NTTK_COL_WIDTH
 #define NTTK_COL_WIDTH 16
 #endif
@@ -48,9 +56,10 @@ __device__ __forceinline__ uint64_t limb_major_vec(uint64_t lp, uint32_t L, uint
 
 __device__ __forceinline__ uint32_t lds_pad(uint32_t r) { return r + (r >> 4); }
 
-template <int LOGM, int NTH = kRowThreads, int LR = kLR>
+template <int LOGM, int NTH = kRowThreads, int LR_ = row_lr(LOGM)>
 struct RowCfg {
-  using S = Steps<LOGM, LR>;
+  using S = Steps<LOGM, LR_>;
+  static constexpr int LR = LR_;
   static constexpr int M = 1 << LOGM;
   static constexpr int T = M / S::R;                    // lanes per row
   static constexpr int V = T >= NTH ? 1 : NTH / T;      // rows per workgroup
@@ -68,10 +77,12 @@ typedef const __attribute__((address_space(4))) VecDesc cVecDesc;
 typedef const __attribute__((address_space(4))) uint64_t cu64;
 
 struct RowRef {
-  gu64* rowp;      // start of this lane's row
-  uint32_t limb;   // its prime
-  uint32_t base;   // N1 + (row within its vector): the row's twiddle base
-  bool valid;      // false for padding rows
+  gu64* rowp;       // start of this lane's row
+  const gu64* srcp; // where the row's input is read (rowp unless the launch is out of place)
+  const gu64* keyp; // the row of the key vector at the same position (key-product launches)
+  uint32_t limb;    // its prime
+  uint32_t base;    // N1 + (row within its vector): the row's twiddle base
+  bool valid;       // false for padding rows
 };
 
 // Row v of this workgroup's tile.  When V divides N1 (every split launch with at least V
@@ -88,18 +99,25 @@ __device__ __forceinline__ RowRef row_ref(const PassArgs& a, uint32_t v) {
     const uint64_t h0 = valid ? (uint64_t)tile * C::V : 0;   // first row, limb-major order
     const uint64_t lp = h0 >> a.logN1;
     gu64* vb;
+    const gu64* sb;
+    const gu64* kb = nullptr;
     uint32_t limb;
     if (a.vecs) {
       const cVecDesc* d = (const cVecDesc*)a.vecs + lp;
       vb = (gu64*)d->ptr;
+      sb = vb;
+      kb = (const gu64*)d->key;
       limb = d->limb;
     } else {
       const uint64_t vec = a.logN1 ? limb_major_vec(lp, a.L, a.P) : lp;
       vb = (gu64*)(a.data + (vec << a.logN));
+      sb = a.src ? (const gu64*)(a.src + (vec << a.logN)) : vb;
+      if (a.key) kb = (const gu64*)(a.key + (vec << a.logN));
       limb = (uint32_t)(vec % a.L);
     }
     const uint32_t r = (uint32_t)(h0 & (N1 - 1)) + v;
-    return RowRef{vb + (size_t)r * C::M, limb, N1 + r, valid};
+    const size_t off = (size_t)r * C::M;
+    return RowRef{vb + off, sb + off, kb ? kb + off : nullptr, limb, N1 + r, valid};
   }
   const uint64_t h = (uint64_t)tile * C::V + v;
   const bool valid = tile < n_tiles && h < rows;
@@ -108,9 +126,13 @@ __device__ __forceinline__ RowRef row_ref(const PassArgs& a, uint32_t v) {
     const uint64_t lp = h >> a.logN1;
     g = ((a.vecs || !a.logN1 ? lp : limb_major_vec(lp, a.L, a.P)) << a.logN1) | (h & (N1 - 1));
   }
-  const VecRef vr = vec_ref(a, g >> a.logN1);
+  const uint64_t vec = g >> a.logN1;
+  const VecRef vr = vec_ref(a, vec);
   const uint32_t r = (uint32_t)(g & (N1 - 1));
-  return RowRef{vr.base + (size_t)r * C::M, vr.limb, N1 + r, valid};
+  const size_t off = (size_t)r * C::M;
+  const gu64* sb = (!a.vecs && a.src) ? (const gu64*)(a.src + (vec << a.logN)) : vr.base;
+  const gu64* kb = a.vecs ? (const gu64*)a.vecs[vec].key : (a.key ? (const gu64*)(a.key + (vec << a.logN)) : nullptr);
+  return RowRef{vr.base + off, sb + off, kb ? kb + off : nullptr, vr.limb, N1 + r, valid};
 }
 
 template <bool FAST, int LOGM, int OTS>
@@ -140,7 +162,7 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void fwd_row_kernel(PassArgs a) {
   uint64_t x[S::R];
   if (valid) {
 #pragma unroll
-    for (int u = 0; u < S::R; ++u) x[u] = rowp[S::template idx<0>(t, u)];
+    for (int u = 0; u < S::R; ++u) x[u] = rr.srcp[S::template idx<0>(t, u)];
   } else {
 #pragma unroll
     for (int u = 0; u < S::R; ++u) x[u] = 0;
@@ -149,7 +171,7 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void fwd_row_kernel(PassArgs a) {
   static_for<0, S::K>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     PreTw<S::R> pre;   // issued before the exchange so the loads overlap the barrier
-    if constexpr (kRowPreload) load_step_twiddles<LOGM, kLR, k, OTS>(pre.w, pre.w2, t, base, tabfn, ot);
+    if constexpr (kRowPreload) load_step_twiddles<LOGM, C::LR, k, OTS>(pre.w, pre.w2, t, base, tabfn, ot);
     if constexpr (k > 0) {
 #pragma unroll
       for (int u = 0; u < S::R; ++u) l[lds_pad(S::template idx<k - 1>(t, u))] = x[u];
@@ -157,8 +179,8 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void fwd_row_kernel(PassArgs a) {
 #pragma unroll
       for (int u = 0; u < S::R; ++u) x[u] = l[lds_pad(S::template idx<k>(t, u))];
     }
-    if constexpr (kRowPreload) ct_step<FAST, LOGM, kLR, k, OTS>(x, t, base, tabfn, ot, md, pre);
-    else ct_step<FAST, LOGM, kLR, k, OTS>(x, t, base, tabfn, ot, md);
+    if constexpr (kRowPreload) ct_step<FAST, LOGM, C::LR, k, OTS>(x, t, base, tabfn, ot, md, pre);
+    else ct_step<FAST, LOGM, C::LR, k, OTS>(x, t, base, tabfn, ot, md);
   });
 
 #pragma unroll
@@ -226,7 +248,7 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void inv_row_kernel(PassArgs a) {
   static_for_down<S::K, 0>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     PreTw<S::R> pre;   // issued before the exchange so the loads overlap the barrier
-    if constexpr (kRowPreload) load_step_twiddles<LOGM, kLR, k, OTS>(pre.w, pre.w2, t, base, tabfn, ot);
+    if constexpr (kRowPreload) load_step_twiddles<LOGM, C::LR, k, OTS>(pre.w, pre.w2, t, base, tabfn, ot);
     if constexpr (k < S::K - 1) {
 #pragma unroll
       for (int u = 0; u < S::R; ++u) l[lds_pad(S::template idx<k + 1>(t, u))] = x[u];
@@ -234,8 +256,8 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void inv_row_kernel(PassArgs a) {
 #pragma unroll
       for (int u = 0; u < S::R; ++u) x[u] = l[lds_pad(S::template idx<k>(t, u))];
     }
-    if constexpr (kRowPreload) gs_step<FAST, LOGM, kLR, k, OTS, SCALE0>(x, t, base, tabfn, ot, md, sc0, sc1, pre);
-    else gs_step<FAST, LOGM, kLR, k, OTS, SCALE0>(x, t, base, tabfn, ot, md, sc0, sc1);
+    if constexpr (kRowPreload) gs_step<FAST, LOGM, C::LR, k, OTS, SCALE0>(x, t, base, tabfn, ot, md, sc0, sc1, pre);
+    else gs_step<FAST, LOGM, C::LR, k, OTS, SCALE0>(x, t, base, tabfn, ot, md, sc0, sc1);
   });
 
   if constexpr (SCALE0) {
@@ -245,6 +267,101 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void inv_row_kernel(PassArgs a) {
   if (valid) {
 #pragma unroll
     for (int u = 0; u < S::R; ++u) rowp[S::template idx<0>(t, u)] = x[u];
+  }
+}
+
+// ----------------------------------------------------------------- row pass with a key product
+// The NTT-based product of Section III-A on the rows of an N1 x N2 split: the forward row
+// stages, the final reduction, the element-wise product with the key (already in the NTT
+// domain, same bit-reversed positions) and the inverse row stages, on registers, in one
+// launch.  The forward row pass leaves each lane holding the positions of its last register
+// step, which are the positions the inverse row pass starts from, so no exchange separates
+// the two halves, and the key is read at those positions (R consecutive elements per lane).
+// af carries the data, the keys and the forward tables; ai the inverse tables and 1/N.
+// SCALE0: single-pass transform (N1 = 1): the whole product happens here.
+template <bool FAST, int LOGM, int OTS, bool SCALE0>
+__global__ __launch_bounds__(RowCfg<LOGM>::NT) void mul_row_kernel(PassArgs af, PassArgs ai) {
+  using A = Arith<FAST>;
+  using C = RowCfg<LOGM>;
+  using S = typename C::S;
+  __shared__ uint64_t lds[C::V * C::PITCH];
+  const uint32_t tid = threadIdx.x, v = tid / C::T, t = tid % C::T;
+  const RowRef rr = row_ref<C>(af, v);
+  const bool valid = rr.valid;
+  const uint32_t limb = rr.limb;
+  const Mod md(((cu64*)af.q)[limb]);
+  const uint32_t base = rr.base;
+  const Tw* tabf = af.tw + ((size_t)limb << af.logN);
+  const Tw* tabi = ai.tw + ((size_t)limb << af.logN);
+  OtTables otf{}, oti{};
+  if constexpr (OTS > 0) {
+    otf.lo = af.ot_lo + ((size_t)limb << af.ot_log2_base);
+    otf.hi = af.ot_hi + ((size_t)limb << (af.logN - af.ot_log2_base));
+    oti.lo = ai.ot_lo + ((size_t)limb << af.ot_log2_base);
+    oti.hi = ai.ot_hi + ((size_t)limb << (af.logN - af.ot_log2_base));
+    otf.logN = oti.logN = af.logN;
+    otf.b = oti.b = af.ot_log2_base;
+  }
+  Tw sc0{}, sc1{};
+  if constexpr (SCALE0) {
+    sc0 = ai.scale[2 * limb];
+    sc1 = ai.scale[2 * limb + 1];
+  }
+  auto tabfnf = [&](uint32_t ix) { return tabf[ix]; };
+  auto tabfni = [&](uint32_t ix) { return tabi[ix]; };
+  uint64_t* l = lds + v * C::PITCH;
+
+  uint64_t x[S::R];
+  if (valid) {
+#pragma unroll
+    for (int u = 0; u < S::R; ++u) x[u] = rr.srcp[S::template idx<0>(t, u)];
+  } else {
+#pragma unroll
+    for (int u = 0; u < S::R; ++u) x[u] = 0;
+  }
+  static_for<0, S::K>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    PreTw<S::R> pre;
+    load_step_twiddles<LOGM, C::LR, k, OTS>(pre.w, pre.w2, t, base, tabfnf, otf);
+    if constexpr (k > 0) {
+#pragma unroll
+      for (int u = 0; u < S::R; ++u) l[lds_pad(S::template idx<k - 1>(t, u))] = x[u];
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < S::R; ++u) x[u] = l[lds_pad(S::template idx<k>(t, u))];
+    }
+    ct_step<FAST, LOGM, C::LR, k, OTS>(x, t, base, tabfnf, otf, md, pre);
+  });
+  // canonical NTT-domain values times the key at the same positions
+  if (valid) {
+    const uint64_t mu = ((cu64*)af.mu)[limb];
+    const uint32_t bits = ((const __attribute__((address_space(4))) uint32_t*)af.bits)[limb];
+#pragma unroll
+    for (int u = 0; u < S::R; ++u)
+      x[u] = mulmod_barrett(A::fwd_final(x[u], md), rr.keyp[S::template idx<S::K - 1>(t, u)], md.q, mu, bits);
+  }
+  static_for_down<S::K, 0>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    PreTw<S::R> pre;
+    load_step_twiddles<LOGM, C::LR, k, OTS>(pre.w, pre.w2, t, base, tabfni, oti);
+    if constexpr (k < S::K - 1) {
+      // the first of these writes goes to the slots this lane read in the forward half's
+      // last exchange, which no other lane reads, so it needs no barrier before it
+#pragma unroll
+      for (int u = 0; u < S::R; ++u) l[lds_pad(S::template idx<k + 1>(t, u))] = x[u];
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < S::R; ++u) x[u] = l[lds_pad(S::template idx<k>(t, u))];
+    }
+    gs_step<FAST, LOGM, C::LR, k, OTS, SCALE0>(x, t, base, tabfni, oti, md, sc0, sc1, pre);
+  });
+  if constexpr (SCALE0) {
+#pragma unroll
+    for (int u = 0; u < S::R; ++u) x[u] = A::inv_final(x[u], md);
+  }
+  if (valid) {
+#pragma unroll
+    for (int u = 0; u < S::R; ++u) rr.rowp[S::template idx<0>(t, u)] = x[u];
   }
 }
 
@@ -283,10 +400,11 @@ __global__ __launch_bounds__(ColCfg<LOGM>::NT) void fwd_col_kernel(PassArgs a) {
   const Tw* tab = a.tw + ((size_t)limb << a.logN);
   for (uint32_t i = tid; i < (uint32_t)C::M; i += C::NT) twl[i] = tab[i];
   gu64* colp = vr.base + cg * C::W + c;
+  const gu64* colsrc = (!a.vecs && a.src) ? (const gu64*)(a.src + (vec << a.logN)) + cg * C::W + c : colp;
 
   uint64_t x[S::R];
 #pragma unroll
-  for (int u = 0; u < S::R; ++u) x[u] = colp[(size_t)S::template idx<0>(t, u) << logN2];
+  for (int u = 0; u < S::R; ++u) x[u] = colsrc[(size_t)S::template idx<0>(t, u) << logN2];
   __syncthreads();
   auto tabfn = [&](uint32_t ix) { return twl[ix]; };
   OtTables ot{};
@@ -447,6 +565,40 @@ hipError_t inv_col(const PassArgs& a, int logm, hipStream_t st) {
   case LM:    \
     return go_inv_col<FAST, LM>(a, st);
     NTTK_COL_CASES(X)
+#undef X
+  }
+  return hipErrorInvalidValue;
+}
+
+template <bool FAST, int LOGM, int OTS, bool SCALE0>
+hipError_t go_mul_row(const PassArgs& af, const PassArgs& ai, hipStream_t st) {
+  using C = RowCfg<LOGM>;
+  const uint64_t rows = af.n_vec << af.logN1;
+  const uint64_t blocks = ((rows + C::V - 1) / C::V + 7) / 8 * 8;
+  hipLaunchKernelGGL((mul_row_kernel<FAST, LOGM, OTS, SCALE0>), dim3((uint32_t)blocks), dim3(C::NT), 0, st, af, ai);
+  return hipGetLastError();
+}
+
+// Row passes with the key product in between (see mul_row_kernel): the whole product when
+// logN1 = 0, else the part between the forward and the inverse column pass.
+template <bool FAST>
+hipError_t mul_rows(const PassArgs& af, const PassArgs& ai, int ots, hipStream_t st) {
+  const int logm = (int)(af.logN - af.logN1);
+  const bool scale0 = af.logN1 == 0;
+  switch (logm) {
+#define X(LM)                                                                                 \
+  case LM:                                                                                    \
+    if (scale0) {                                                                             \
+      if (ots == 0) return go_mul_row<FAST, LM, 0, true>(af, ai, st);                         \
+      if constexpr (LM >= 2) if (ots == 1) return go_mul_row<FAST, LM, 1, true>(af, ai, st);  \
+      if constexpr (LM >= 3) if (ots == 2) return go_mul_row<FAST, LM, 2, true>(af, ai, st);  \
+    } else {                                                                                  \
+      if (ots == 0) return go_mul_row<FAST, LM, 0, false>(af, ai, st);                        \
+      if (ots == 1) return go_mul_row<FAST, LM, 1, false>(af, ai, st);                        \
+      if (ots == 2) return go_mul_row<FAST, LM, 2, false>(af, ai, st);                        \
+    }                                                                                         \
+    return hipErrorInvalidValue;
+    NTTK_ROW_CASES(X)
 #undef X
   }
   return hipErrorInvalidValue;

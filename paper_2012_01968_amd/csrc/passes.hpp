@@ -45,6 +45,14 @@ struct PassArgs {
   uint32_t logN1;        // log2 of the column-pass size (0: single pass)
   uint32_t ot_log2_base; // log2 B
   uint32_t fast;         // every prime below 2^60: the Arith<true> policy applies
+  // Dense launches only: the first pass of a forward transform may read its input from
+  // `src` (same [n_vec][N] layout) instead of `data` (out of place); null = in place.
+  const uint64_t* src;
+  // Key-product launches (mul_row): the key vector of vector v is key + v*N (dense) or the
+  // list's key pointer, multiplied in with Barrett constants mu[l], bits[l].
+  const uint64_t* key;
+  const uint64_t* mu;
+  const uint32_t* bits;
 };
 
 // Base address and limb of vector `vec` of a launch: dense [P][L][N] batches place vector

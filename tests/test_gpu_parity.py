@@ -214,6 +214,37 @@ def test_pointwise_and_polymul(logN):
         plan.destroy()
 
 
+@pytest.mark.parametrize("logN,bits,opts", [
+    (8, 62, {}),                                                     # single pass, exact quotients
+    (13, 60, dict(twiddle_mode=2, ot_stages=2, log2_n1=-1)),         # single pass with OT
+    (13, 61, dict(log2_n1=6)),
+    (14, 60, dict(twiddle_mode=2, ot_stages=1)),
+    (16, 62, dict(twiddle_mode=2, ot_stages=2, ot_log2_base=8)),
+    (17, 60, dict(log2_n1=10)),
+    (16, 60, dict(kernel_path=2)),                                   # fused-path plan: separate launches
+])
+def test_polymul_paths(logN, bits, opts):
+    """The product's launch sequences: NTT(b) out of place, a's forward column pass out of
+    place, then one launch for the row passes with the key product, then the inverse column
+    pass (or a single launch at single-pass sizes)."""
+    N, L, P = 1 << logN, 3, 2
+    primes, psis, a = make(N, L, P, bits, 750 + logN)
+    b = synth.residue_batch(751 + logN, primes, N, P)
+    plan = ntt.ntt_plan_create(N, primes, **opts)
+    try:
+        da, db, dc = dev(a), dev(b), dev(np.zeros_like(a))
+        ntt.ntt_polymul_negacyclic(plan, da, db, dc)
+        torch.cuda.synchronize()
+        want = oracle.polymul(a, b, primes, psis, THREADS)
+        assert np.array_equal(host(dc), want), f"N=2^{logN} {opts}"
+        assert np.array_equal(host(da), a) and np.array_equal(host(db), b)
+        ntt.ntt_polymul_negacyclic(plan, da, db, da)   # in place on a
+        torch.cuda.synchronize()
+        assert np.array_equal(host(da), want)
+    finally:
+        plan.destroy()
+
+
 # ------------------------------------------------------------------ benchmark workloads at full size
 
 def test_config1_plain_small():
@@ -431,3 +462,19 @@ def test_batch_assign_reuse():
             batch.destroy()
         for p in plans.values():
             p.destroy()
+
+
+def test_config3_polymul_entry_point():
+    """N=2^17, L=60 (seed 3), OT on: the negacyclic product of two 2-polynomial operands through
+    ntt_polymul_negacyclic, against the oracle."""
+    N, L = 1 << 17, 60
+    primes, psis, data = make(N, L, 4, 60, 3)
+    plan = ntt.ntt_plan_create(N, primes, twiddle_mode=ntt.TWIDDLE_OT, ot_stages=2)
+    try:
+        da, db = dev(data[:2]), dev(data[2:])
+        dc = torch.empty_like(da)
+        ntt.ntt_polymul_negacyclic(plan, da, db, dc)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(dc), oracle.polymul(data[:2], data[2:], primes, psis, THREADS))
+    finally:
+        plan.destroy()
