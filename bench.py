@@ -146,6 +146,7 @@ def main() -> int:
     ap.add_argument("--serve-high-rate", type=float, default=12000.0,
                     help="arrival rate of a second, 5-second stream above the per-request path's capacity (0 skips)")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch section")
+    ap.add_argument("--no-polymul", action="store_true", help="skip the large-parameter product section")
     ap.add_argument("--profile-run", action="store_true",
                     help="counter-collection driver: --steps steps of one twiddle mode (no timing, no JSON), "
                          "then one plain device copy of a ciphertext for the counters' byte calibration")
@@ -305,6 +306,7 @@ def main() -> int:
         results[m]["plan"].destroy()
     del bufs
     torch.cuda.empty_cache()
+    polymul = None if args.no_polymul else polymul_bench(args)
     uneven = None if args.no_uneven else uneven_batch_bench(args)
     serving = serve_bench(args) if args.serve_seconds > 0 else None
 
@@ -327,12 +329,76 @@ def main() -> int:
         "modes_us_per_step": {m: round(results[m]["ms"] * 1e3, 2) for m in results},
         "roundtrip_ok": r["roundtrip_ok"],
         "autotune": tuned,
+        "polymul": polymul,
         "uneven_batch": uneven,
         "serving": serving,
         "source_hash": src_hash,
     }
     print(json.dumps(out), flush=True)
     return 0
+
+
+POLYMUL = dict(logN=17, L=60, polys=2, bits=60, seed=3)
+
+
+def polymul_bench(args):
+    """Negacyclic products at N = 2^17, L = 60: c = a * b for 2-polynomial operands a and b
+    (a ciphertext pair: forward NTT of a and of b, element-wise product, inverse NTT), with
+    table and OT twiddles.  Reports time per product, the twiddle bytes each plan reads per
+    product, and checks the product against the oracle."""
+    import torch
+    import oracle
+    import synth
+    import paper_2012_01968_amd as ntt
+
+    cfg = POLYMUL
+    N, L, P = 1 << cfg["logN"], cfg["L"], cfg["polys"]
+    primes = synth.gen_primes(cfg["seed"], N, cfg["bits"], L)
+    host = synth.residue_batch(cfg["seed"], primes, N, 2 * P)
+    da = torch.from_numpy(np.ascontiguousarray(host[:P]).view(np.int64)).to("cuda")
+    db = torch.from_numpy(np.ascontiguousarray(host[P:]).view(np.int64)).to("cuda")
+    dc = torch.empty_like(da)
+    limb_ntts = 3 * P * L                     # NTT(a), NTT(b), inverse of the product
+    out = {"workload": f"c = a * b mod (X^N + 1, q_l), N=2^{cfg['logN']}, L={L} primes in [2^59,2^60) "
+                       f"(seed {cfg['seed']}), a and b of {P} polys each ({limb_ntts} limb-NTTs per product)"}
+    modes = {"table": dict(kernel_path=1), "ot": dict(kernel_path=1, twiddle_mode=2, ot_stages=2)}
+    if not args.no_tune:
+        modes["tuned"] = tune_shape(N, primes, P)["opts"]
+    steps = max(5, min(args.steps, 50))
+    want = None
+    for name, opts in modes.items():
+        plan = ntt.ntt_plan_create(N, primes, **opts)
+        info = ntt.ntt_plan_get_info(plan)
+        ots = info["ot_stages"] if info["twiddle_mode"] == ntt.TWIDDLE_OT else 0
+        step = lambda i: ntt.ntt_polymul_negacyclic(plan, da, db, dc)
+        ramp(step, args.ramp_ms)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for i in range(steps):
+            step(i)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        if want is None:
+            want = oracle.polymul(host[:P], host[P:], primes, oracle.roots(primes, N),
+                                  max(1, min(16, os.cpu_count() or 1)))
+        ok = bool(np.array_equal(dc.cpu().numpy().view(np.uint64), want))
+        # twiddle bytes read per product: forward column and row passes of a and of b, the
+        # fused rows (forward and inverse row twiddles) and the inverse column pass
+        n1 = info["log2_n1"]
+        col = twiddle_bytes("col", N, L, n1, ots) if n1 else 0
+        row = twiddle_bytes("row", N, L, n1, ots)
+        tw = 3 * col + 3 * row if n1 else 3 * row
+        out[name] = {"plan": variant_key(info, ots), "ms_per_product": round(ms, 4),
+                     "limb_ntts_per_s": round(limb_ntts / (ms * 1e-3), 1),
+                     "twiddle_mb_per_product": round(tw / 1e6, 2), "matches_oracle": ok}
+        log(f"[polymul {name}] {ms:.3f} ms/product  {limb_ntts / ms / 1e3:.3f} M limb-NTTs/s  "
+            f"twiddles {tw / 1e6:.1f} MB/product  oracle={'ok' if ok else 'MISMATCH'}")
+        plan.destroy()
+    del da, db, dc
+    torch.cuda.empty_cache()
+    return out
 
 
 UNEVEN = dict(polys=256, logNs=(13, 14, 15, 16, 17), weights=(0.1, 0.2, 0.3, 0.3, 0.1), L=(4, 60), bits=60,

@@ -96,26 +96,33 @@ __device__ __forceinline__ RowRef row_ref(const PassArgs& a, uint32_t v) {
   const uint32_t N1 = 1u << a.logN1;
   if ((uint32_t)C::V <= N1) {
     const bool valid = tile < n_tiles;
-    const uint64_t h0 = valid ? (uint64_t)tile * C::V : 0;   // first row, limb-major order
-    const uint64_t lp = h0 >> a.logN1;
+    const uint32_t tl = valid ? tile : 0;
     gu64* vb;
     const gu64* sb;
     const gu64* kb = nullptr;
-    uint32_t limb;
+    uint32_t limb, r0;
     if (a.vecs) {
-      const cVecDesc* d = (const cVecDesc*)a.vecs + lp;
+      const uint64_t h0 = (uint64_t)tl * C::V;   // list order
+      const cVecDesc* d = (const cVecDesc*)a.vecs + (h0 >> a.logN1);
       vb = (gu64*)d->ptr;
       sb = vb;
       kb = (const gu64*)d->key;
       limb = d->limb;
+      r0 = (uint32_t)(h0 & (N1 - 1));
     } else {
-      const uint64_t vec = a.logN1 ? limb_major_vec(lp, a.L, a.P) : lp;
+      // tile order (limb, row group, polynomial): the polynomials of one limb take the same
+      // rows back to back, so a row's twiddles are fetched once into L2 for all of them
+      const uint32_t log_groups = a.logN1 - (uint32_t)__builtin_ctz((uint32_t)C::V);
+      const uint32_t p = tl % a.P, rest = tl / a.P;
+      const uint32_t l = rest >> log_groups;
+      r0 = (rest & ((1u << log_groups) - 1u)) * C::V;
+      const uint64_t vec = (uint64_t)p * a.L + l;
       vb = (gu64*)(a.data + (vec << a.logN));
       sb = a.src ? (const gu64*)(a.src + (vec << a.logN)) : vb;
       if (a.key) kb = (const gu64*)(a.key + (vec << a.logN));
-      limb = (uint32_t)(vec % a.L);
+      limb = l;
     }
-    const uint32_t r = (uint32_t)(h0 & (N1 - 1)) + v;
+    const uint32_t r = r0 + v;
     const size_t off = (size_t)r * C::M;
     return RowRef{vb + off, sb + off, kb ? kb + off : nullptr, limb, N1 + r, valid};
   }
