@@ -478,3 +478,44 @@ def test_config3_polymul_entry_point():
         assert np.array_equal(host(dc), oracle.polymul(data[:2], data[2:], primes, psis, THREADS))
     finally:
         plan.destroy()
+
+
+@pytest.mark.parametrize("mode", ["plain", "grouped", "graph"])
+def test_batch_mulkey_ot_and_wide_plans(mode):
+    """Forward, key product, inverse jobs on OT plans (single pass and split) and on a plan of
+    61-bit primes (exact quotients), with limb prefixes; every result against the oracle."""
+    specs = [  # (logN, bits, plan options, [(limbs, polys), ...])
+        (12, 60, dict(twiddle_mode=ntt.TWIDDLE_OT, ot_stages=2), [(3, 2), (1, 1)]),
+        (14, 60, dict(twiddle_mode=ntt.TWIDDLE_OT, ot_stages=1, ot_log2_base=8), [(4, 1), (2, 3)]),
+        (13, 61, dict(log2_n1=6), [(4, 2)]),
+    ]
+    plans, jobs, bufs, want = [], [], [], []
+    try:
+        for si, (logN, bits, opts, shapes) in enumerate(specs):
+            N = 1 << logN
+            chain = synth.gen_primes(1700 + si, N, bits, 4)
+            plan = ntt.ntt_plan_create(N, chain, **opts)
+            plans.append(plan)
+            key_coeff = synth.residue_batch(1710 + si, chain, N, 1).reshape(4, N)
+            key_ntt = oracle.forward(key_coeff, chain, oracle.roots(chain, N), THREADS)
+            dk = dev(key_ntt)
+            for k, (limbs, polys) in enumerate(shapes):
+                primes = chain[:limbs]
+                data = synth.residue_batch(1720 + 10 * si + k, primes, N, polys)
+                w = oracle.polymul(data.reshape(polys * limbs, N), np.tile(key_coeff[:limbs], (polys, 1)), primes,
+                                   oracle.roots(primes, N), THREADS).reshape(data.shape)
+                d = dev(data)
+                bufs.append((d, dk))
+                want.append(w)
+                jobs.append((plan, d, polys, limbs if limbs < 4 else 0,
+                             ntt.OP_FORWARD | ntt.OP_MULKEY | ntt.OP_INVERSE, dk))
+        batch = ntt.ntt_batch_create(jobs)
+        m = {"plain": ntt.BATCH_PLAIN, "grouped": ntt.BATCH_GROUPED, "graph": ntt.BATCH_GRAPH}[mode]
+        ntt.ntt_batch_run(batch, m)
+        torch.cuda.synchronize()
+        for (d, _), w in zip(bufs, want):
+            assert np.array_equal(host(d), w)
+        batch.destroy()
+    finally:
+        for p in plans:
+            p.destroy()
