@@ -81,6 +81,7 @@ struct ntt_plan_s {
   std::vector<uint64_t> primes, psis;
 
   uint64_t* d_q = nullptr;
+  uint64_t* d_mc = nullptr;   // [L][8] per-prime constants of the split passes
   Tw* d_tw_fwd = nullptr;
   Tw* d_tw_inv = nullptr;
   Tw* d_ot_lo_fwd = nullptr;
@@ -107,7 +108,7 @@ struct ntt_plan_s {
       (void)hipEventSynchronize(fused_ev);
       (void)hipEventDestroy(fused_ev);
     }
-    void* ptrs[] = {d_q, d_tw_fwd, d_tw_inv, d_ot_lo_fwd, d_ot_hi_fwd, d_ot_lo_inv, d_ot_hi_inv,
+    void* ptrs[] = {d_q, d_mc, d_tw_fwd, d_tw_inv, d_ot_lo_fwd, d_ot_hi_fwd, d_ot_lo_inv, d_ot_hi_inv,
                     d_scale, d_mu, d_bits, scratch, d_ctr};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
@@ -121,6 +122,7 @@ struct ntt_plan_s {
     a.ot_lo = inverse ? d_ot_lo_inv : d_ot_lo_fwd;
     a.ot_hi = inverse ? d_ot_hi_inv : d_ot_hi_fwd;
     a.q = d_q;
+    a.mc = d_mc;
     a.scale = d_scale;
     const uint32_t Lu = limbs ? limbs : L;
     a.n_vec = (uint64_t)n_polys * Lu;
@@ -268,10 +270,28 @@ static ntt_status build_plan(ntt_plan_s* p, uint32_t N, const uint64_t* primes, 
   for (uint32_t l = 0; l < L; ++l)
     if (bad[l]) return fail(NTT_ERR_PRIME, "no primitive 2N-th root found mod " + std::to_string(p->primes[l]));
   p->psis = psis;
+  std::vector<uint64_t> mod_consts(8 * (size_t)L, 0);
+  for (uint32_t l = 0; l < L; ++l) {
+    const uint64_t q = p->primes[l];
+    uint64_t* c = &mod_consts[8 * (size_t)l];
+    c[0] = q;
+    c[1] = q << 1;
+    c[2] = q << 2;
+    c[3] = 0 - q;
+    c[4] = 0 - (q << 1);
+    c[5] = 0 - (q << 2);
+    c[6] = 0 - (q << 3);
+    uint32_t fa, fb;
+    const float fah = nttk::quot_factor_hi(q), fbh = nttk::quot_factor_lo(q);
+    std::memcpy(&fa, &fah, 4);
+    std::memcpy(&fb, &fbh, 4);
+    c[7] = (uint64_t)fa | ((uint64_t)fb << 32);
+  }
 
   if (hipGetDevice(&p->device) != hipSuccess) return fail(NTT_ERR_HIP, "hipGetDevice failed");
   hipError_t e;
-  if ((e = upload(&p->d_q, p->primes)) != hipSuccess || (e = upload(&p->d_tw_fwd, tw_fwd)) != hipSuccess ||
+  if ((e = upload(&p->d_q, p->primes)) != hipSuccess || (e = upload(&p->d_mc, mod_consts)) != hipSuccess ||
+      (e = upload(&p->d_tw_fwd, tw_fwd)) != hipSuccess ||
       (e = upload(&p->d_tw_inv, tw_inv)) != hipSuccess || (e = upload(&p->d_ot_lo_fwd, ot_lo_f)) != hipSuccess ||
       (e = upload(&p->d_ot_hi_fwd, ot_hi_f)) != hipSuccess || (e = upload(&p->d_ot_lo_inv, ot_lo_i)) != hipSuccess ||
       (e = upload(&p->d_ot_hi_inv, ot_hi_i)) != hipSuccess || (e = upload(&p->d_scale, scale)) != hipSuccess ||

@@ -76,7 +76,7 @@ __device__ __forceinline__ void fwd_col_tile(const PassArgs& a, uint32_t v, uint
   using S = typename F::SC;
   const uint32_t tid = threadIdx.x, c = tid % F::C, t = tid / F::C;
   const uint32_t limb = v % a.L;
-  const Mod md(a.q[limb]);
+  const Mod md = Mod::load(a.mc + 8 * (size_t)limb);
   const Tw* tab = a.tw + ((size_t)limb << a.logN);
   for (uint32_t i = tid; i < (uint32_t)F::M1; i += kFusedThreads) twl[i] = tab[i];
   uint64_t* colp = a.data + ((uint64_t)v << a.logN) + cg * F::C + c;
@@ -109,7 +109,7 @@ __device__ __forceinline__ void fwd_row_tile(const PassArgs& a, uint32_t v, uint
   using A = Arith<FAST>;
   const uint32_t tid = threadIdx.x, vr = tid / RC::T, t = tid % RC::T;
   const uint32_t limb = v % a.L;
-  const Mod md(a.q[limb]);
+  const Mod md = Mod::load(a.mc + 8 * (size_t)limb);
   const uint32_t row = rt * RC::V + vr;
   const uint32_t base = (uint32_t)F::M1 + row;
   const Tw* tab = a.tw + ((size_t)limb << a.logN);
@@ -130,10 +130,10 @@ __device__ __forceinline__ void fwd_row_tile(const PassArgs& a, uint32_t v, uint
     constexpr int k = decltype(kc)::value;
     if constexpr (k > 0) {
 #pragma unroll
-      for (int u = 0; u < S::R; ++u) l[lds_pad(S::template idx<k - 1>(t, u))] = x[u];
+      for (int u = 0; u < S::R; ++u) l[RC::at(S::template idx<k - 1>(t, u))] = x[u];
       __syncthreads();
 #pragma unroll
-      for (int u = 0; u < S::R; ++u) x[u] = l[lds_pad(S::template idx<k>(t, u))];
+      for (int u = 0; u < S::R; ++u) x[u] = l[RC::at(S::template idx<k>(t, u))];
     }
     ct_step<FAST, LOGM2, kFusedLR, k, OTS>(x, t, base, tabfn, ot, md);
   });
@@ -141,10 +141,10 @@ __device__ __forceinline__ void fwd_row_tile(const PassArgs& a, uint32_t v, uint
   for (int u = 0; u < S::R; ++u) x[u] = A::fwd_final(x[u], md);
   if constexpr (S::K > 1) {
 #pragma unroll
-    for (int u = 0; u < S::R; ++u) l[lds_pad(S::template idx<S::K - 1>(t, u))] = x[u];
+    for (int u = 0; u < S::R; ++u) l[RC::at(S::template idx<S::K - 1>(t, u))] = x[u];
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < S::R; ++u) x[u] = l[lds_pad(S::template idx<0>(t, u))];
+    for (int u = 0; u < S::R; ++u) x[u] = l[RC::at(S::template idx<0>(t, u))];
   }
 #pragma unroll
   for (int u = 0; u < S::R; ++u) rowp[S::template idx<0>(t, u)] = x[u];
@@ -159,7 +159,7 @@ __device__ __forceinline__ void inv_row_tile(const PassArgs& a, uint32_t v, uint
   using S = typename RC::S;
   const uint32_t tid = threadIdx.x, vr = tid / RC::T, t = tid % RC::T;
   const uint32_t limb = v % a.L;
-  const Mod md(a.q[limb]);
+  const Mod md = Mod::load(a.mc + 8 * (size_t)limb);
   const uint32_t row = rt * RC::V + vr;
   const uint32_t base = (uint32_t)F::M1 + row;
   const Tw* tab = a.tw + ((size_t)limb << a.logN);
@@ -179,19 +179,19 @@ __device__ __forceinline__ void inv_row_tile(const PassArgs& a, uint32_t v, uint
   for (int u = 0; u < S::R; ++u) x[u] = rowp[S::template idx<0>(t, u)];
   if constexpr (S::K > 1) {
 #pragma unroll
-    for (int u = 0; u < S::R; ++u) l[lds_pad(S::template idx<0>(t, u))] = x[u];
+    for (int u = 0; u < S::R; ++u) l[RC::at(S::template idx<0>(t, u))] = x[u];
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < S::R; ++u) x[u] = l[lds_pad(S::template idx<S::K - 1>(t, u))];
+    for (int u = 0; u < S::R; ++u) x[u] = l[RC::at(S::template idx<S::K - 1>(t, u))];
   }
   static_for_down<S::K, 0>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     if constexpr (k < S::K - 1) {
 #pragma unroll
-      for (int u = 0; u < S::R; ++u) l[lds_pad(S::template idx<k + 1>(t, u))] = x[u];
+      for (int u = 0; u < S::R; ++u) l[RC::at(S::template idx<k + 1>(t, u))] = x[u];
       __syncthreads();
 #pragma unroll
-      for (int u = 0; u < S::R; ++u) x[u] = l[lds_pad(S::template idx<k>(t, u))];
+      for (int u = 0; u < S::R; ++u) x[u] = l[RC::at(S::template idx<k>(t, u))];
     }
     gs_step<FAST, LOGM2, kFusedLR, k, OTS, false>(x, t, base, tabfn, ot, md, sc, sc);
   });
@@ -206,7 +206,7 @@ __device__ __forceinline__ void inv_col_tile(const PassArgs& a, uint32_t v, uint
   using A = Arith<FAST>;
   const uint32_t tid = threadIdx.x, c = tid % F::C, t = tid / F::C;
   const uint32_t limb = v % a.L;
-  const Mod md(a.q[limb]);
+  const Mod md = Mod::load(a.mc + 8 * (size_t)limb);
   const Tw* tab = a.tw + ((size_t)limb << a.logN);
   for (uint32_t i = tid; i < (uint32_t)F::M1; i += kFusedThreads) twl[i] = tab[i];
   const Tw sc0 = a.scale[2 * limb], sc1 = a.scale[2 * limb + 1];

@@ -65,6 +65,8 @@ struct RowCfg {
   static constexpr int V = T >= NTH ? 1 : NTH / T;      // rows per workgroup
   static constexpr int NT = V * T;
   static constexpr int PITCH = M >= 16 ? M + M / 16 : M;
+  // LDS slot of element r of a row: one pad slot per 16 elements.
+  static __device__ __forceinline__ uint32_t at(uint32_t r) { return lds_pad(r); }
 };
 
 // ----------------------------------------------------------------------------- row pass
@@ -152,7 +154,7 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void fwd_row_kernel(PassArgs a) {
   const RowRef rr = row_ref<C>(a, v);
   const bool valid = rr.valid;
   const uint32_t limb = rr.limb;
-  const Mod md(((cu64*)a.q)[limb]);
+  const Mod md = Mod::load((cu64*)a.mc + 8 * (size_t)limb);
   const uint32_t base = rr.base;
   const Tw* tab = a.tw + ((size_t)limb << a.logN);
   OtTables ot{};
@@ -181,10 +183,10 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void fwd_row_kernel(PassArgs a) {
     if constexpr (kRowPreload) load_step_twiddles<LOGM, C::LR, k, OTS>(pre.w, pre.w2, t, base, tabfn, ot);
     if constexpr (k > 0) {
 #pragma unroll
-      for (int u = 0; u < S::R; ++u) l[lds_pad(S::template idx<k - 1>(t, u))] = x[u];
+      for (int u = 0; u < S::R; ++u) l[C::at(S::template idx<k - 1>(t, u))] = x[u];
       __syncthreads();
 #pragma unroll
-      for (int u = 0; u < S::R; ++u) x[u] = l[lds_pad(S::template idx<k>(t, u))];
+      for (int u = 0; u < S::R; ++u) x[u] = l[C::at(S::template idx<k>(t, u))];
     }
     if constexpr (kRowPreload) ct_step<FAST, LOGM, C::LR, k, OTS>(x, t, base, tabfn, ot, md, pre);
     else ct_step<FAST, LOGM, C::LR, k, OTS>(x, t, base, tabfn, ot, md);
@@ -194,10 +196,10 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void fwd_row_kernel(PassArgs a) {
   for (int u = 0; u < S::R; ++u) x[u] = A::fwd_final(x[u], md);
   if constexpr (S::K > 1) {
 #pragma unroll
-    for (int u = 0; u < S::R; ++u) l[lds_pad(S::template idx<S::K - 1>(t, u))] = x[u];
+    for (int u = 0; u < S::R; ++u) l[C::at(S::template idx<S::K - 1>(t, u))] = x[u];
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < S::R; ++u) x[u] = l[lds_pad(S::template idx<0>(t, u))];
+    for (int u = 0; u < S::R; ++u) x[u] = l[C::at(S::template idx<0>(t, u))];
   }
   if (valid) {
 #pragma unroll
@@ -217,7 +219,7 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void inv_row_kernel(PassArgs a) {
   const RowRef rr = row_ref<C>(a, v);
   const bool valid = rr.valid;
   const uint32_t limb = rr.limb;
-  const Mod md(((cu64*)a.q)[limb]);
+  const Mod md = Mod::load((cu64*)a.mc + 8 * (size_t)limb);
   const uint32_t base = rr.base;
   const Tw* tab = a.tw + ((size_t)limb << a.logN);
   OtTables ot{};
@@ -246,10 +248,10 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void inv_row_kernel(PassArgs a) {
   }
   if constexpr (S::K > 1) {
 #pragma unroll
-    for (int u = 0; u < S::R; ++u) l[lds_pad(S::template idx<0>(t, u))] = x[u];
+    for (int u = 0; u < S::R; ++u) l[C::at(S::template idx<0>(t, u))] = x[u];
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < S::R; ++u) x[u] = l[lds_pad(S::template idx<S::K - 1>(t, u))];
+    for (int u = 0; u < S::R; ++u) x[u] = l[C::at(S::template idx<S::K - 1>(t, u))];
   }
 
   static_for_down<S::K, 0>([&](auto kc) {
@@ -258,10 +260,10 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void inv_row_kernel(PassArgs a) {
     if constexpr (kRowPreload) load_step_twiddles<LOGM, C::LR, k, OTS>(pre.w, pre.w2, t, base, tabfn, ot);
     if constexpr (k < S::K - 1) {
 #pragma unroll
-      for (int u = 0; u < S::R; ++u) l[lds_pad(S::template idx<k + 1>(t, u))] = x[u];
+      for (int u = 0; u < S::R; ++u) l[C::at(S::template idx<k + 1>(t, u))] = x[u];
       __syncthreads();
 #pragma unroll
-      for (int u = 0; u < S::R; ++u) x[u] = l[lds_pad(S::template idx<k>(t, u))];
+      for (int u = 0; u < S::R; ++u) x[u] = l[C::at(S::template idx<k>(t, u))];
     }
     if constexpr (kRowPreload) gs_step<FAST, LOGM, C::LR, k, OTS, SCALE0>(x, t, base, tabfn, ot, md, sc0, sc1, pre);
     else gs_step<FAST, LOGM, C::LR, k, OTS, SCALE0>(x, t, base, tabfn, ot, md, sc0, sc1);
@@ -296,7 +298,7 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void mul_row_kernel(PassArgs af, 
   const RowRef rr = row_ref<C>(af, v);
   const bool valid = rr.valid;
   const uint32_t limb = rr.limb;
-  const Mod md(((cu64*)af.q)[limb]);
+  const Mod md = Mod::load((cu64*)af.mc + 8 * (size_t)limb);
   const uint32_t base = rr.base;
   const Tw* tabf = af.tw + ((size_t)limb << af.logN);
   const Tw* tabi = ai.tw + ((size_t)limb << af.logN);
@@ -332,10 +334,10 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void mul_row_kernel(PassArgs af, 
     load_step_twiddles<LOGM, C::LR, k, OTS>(pre.w, pre.w2, t, base, tabfnf, otf);
     if constexpr (k > 0) {
 #pragma unroll
-      for (int u = 0; u < S::R; ++u) l[lds_pad(S::template idx<k - 1>(t, u))] = x[u];
+      for (int u = 0; u < S::R; ++u) l[C::at(S::template idx<k - 1>(t, u))] = x[u];
       __syncthreads();
 #pragma unroll
-      for (int u = 0; u < S::R; ++u) x[u] = l[lds_pad(S::template idx<k>(t, u))];
+      for (int u = 0; u < S::R; ++u) x[u] = l[C::at(S::template idx<k>(t, u))];
     }
     ct_step<FAST, LOGM, C::LR, k, OTS>(x, t, base, tabfnf, otf, md, pre);
   });
@@ -355,10 +357,10 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void mul_row_kernel(PassArgs af, 
       // the first of these writes goes to the slots this lane read in the forward half's
       // last exchange, which no other lane reads, so it needs no barrier before it
 #pragma unroll
-      for (int u = 0; u < S::R; ++u) l[lds_pad(S::template idx<k + 1>(t, u))] = x[u];
+      for (int u = 0; u < S::R; ++u) l[C::at(S::template idx<k + 1>(t, u))] = x[u];
       __syncthreads();
 #pragma unroll
-      for (int u = 0; u < S::R; ++u) x[u] = l[lds_pad(S::template idx<k>(t, u))];
+      for (int u = 0; u < S::R; ++u) x[u] = l[C::at(S::template idx<k>(t, u))];
     }
     gs_step<FAST, LOGM, C::LR, k, OTS, SCALE0>(x, t, base, tabfni, oti, md, sc0, sc1, pre);
   });
@@ -385,6 +387,7 @@ struct ColCfg {
   static constexpr int W = kColWidth * T > 1024 ? 1024 / T : kColWidth;   // at most 1024 lanes
   static constexpr int NT = W * T;
   static constexpr int PITCH = W;         // LDS elements per matrix row
+  static __device__ __forceinline__ uint32_t at(uint32_t r) { return r * PITCH; }   // LDS offset of row r
 };
 
 template <bool FAST, int LOGM>
@@ -403,15 +406,16 @@ __global__ __launch_bounds__(ColCfg<LOGM>::NT) void fwd_col_kernel(PassArgs a) {
   const uint32_t cg = tile % groups;
   const VecRef vr = vec_ref(a, vec);
   const uint32_t limb = vr.limb;
-  const Mod md(a.q[limb]);
+  const Mod md = Mod::load((cu64*)a.mc + 8 * (size_t)limb);
   const Tw* tab = a.tw + ((size_t)limb << a.logN);
-  for (uint32_t i = tid; i < (uint32_t)C::M; i += C::NT) twl[i] = tab[i];
   gu64* colp = vr.base + cg * C::W + c;
   const gu64* colsrc = (!a.vecs && a.src) ? (const gu64*)(a.src + (vec << a.logN)) + cg * C::W + c : colp;
 
+  // the column loads go out first, so that the twiddle staging waits on both at once
   uint64_t x[S::R];
 #pragma unroll
   for (int u = 0; u < S::R; ++u) x[u] = colsrc[(size_t)S::template idx<0>(t, u) << logN2];
+  for (uint32_t i = tid; i < (uint32_t)C::M; i += C::NT) twl[i] = tab[i];
   __syncthreads();
   auto tabfn = [&](uint32_t ix) { return twl[ix]; };
   OtTables ot{};
@@ -420,10 +424,10 @@ __global__ __launch_bounds__(ColCfg<LOGM>::NT) void fwd_col_kernel(PassArgs a) {
     constexpr int k = decltype(kc)::value;
     if constexpr (k > 0) {
 #pragma unroll
-      for (int u = 0; u < S::R; ++u) lds[S::template idx<k - 1>(t, u) * C::PITCH + c] = x[u];
+      for (int u = 0; u < S::R; ++u) lds[C::at(S::template idx<k - 1>(t, u)) + c] = x[u];
       __syncthreads();
 #pragma unroll
-      for (int u = 0; u < S::R; ++u) x[u] = lds[S::template idx<k>(t, u) * C::PITCH + c];
+      for (int u = 0; u < S::R; ++u) x[u] = lds[C::at(S::template idx<k>(t, u)) + c];
     }
     ct_step<FAST, LOGM, kLR, k, 0>(x, t, 1u, tabfn, ot, md);
   });
@@ -449,15 +453,15 @@ __global__ __launch_bounds__(ColCfg<LOGM>::NT) void inv_col_kernel(PassArgs a) {
   const uint32_t cg = tile % groups;
   const VecRef vr = vec_ref(a, vec);
   const uint32_t limb = vr.limb;
-  const Mod md(a.q[limb]);
+  const Mod md = Mod::load((cu64*)a.mc + 8 * (size_t)limb);
   const Tw* tab = a.tw + ((size_t)limb << a.logN);
-  for (uint32_t i = tid; i < (uint32_t)C::M; i += C::NT) twl[i] = tab[i];
   const Tw sc0 = a.scale[2 * limb], sc1 = a.scale[2 * limb + 1];
   gu64* colp = vr.base + cg * C::W + c;
 
   uint64_t x[S::R];
 #pragma unroll
   for (int u = 0; u < S::R; ++u) x[u] = colp[(size_t)S::template idx<S::K - 1>(t, u) << logN2];
+  for (uint32_t i = tid; i < (uint32_t)C::M; i += C::NT) twl[i] = tab[i];
   __syncthreads();
   auto tabfn = [&](uint32_t ix) { return twl[ix]; };
   OtTables ot{};
@@ -466,10 +470,10 @@ __global__ __launch_bounds__(ColCfg<LOGM>::NT) void inv_col_kernel(PassArgs a) {
     constexpr int k = decltype(kc)::value;
     if constexpr (k < S::K - 1) {
 #pragma unroll
-      for (int u = 0; u < S::R; ++u) lds[S::template idx<k + 1>(t, u) * C::PITCH + c] = x[u];
+      for (int u = 0; u < S::R; ++u) lds[C::at(S::template idx<k + 1>(t, u)) + c] = x[u];
       __syncthreads();
 #pragma unroll
-      for (int u = 0; u < S::R; ++u) x[u] = lds[S::template idx<k>(t, u) * C::PITCH + c];
+      for (int u = 0; u < S::R; ++u) x[u] = lds[C::at(S::template idx<k>(t, u)) + c];
     }
     gs_step<FAST, LOGM, kLR, k, 0, true>(x, t, 1u, tabfn, ot, md, sc0, sc1);
   });

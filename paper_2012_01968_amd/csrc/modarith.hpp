@@ -35,11 +35,37 @@ struct Tw {  // a twiddle and its Shoup companion, stored as one 16-byte entry
   uint64_t w, wb;
 };
 
+// Quotient-estimate factors 2^32/q and 1/q, rounded to float after scaling by (1 - 2^-20):
+// the bias keeps every float estimate of x/q at or below the true value (see fwd_final).
+__host__ __device__ inline float quot_factor_hi(uint64_t q) {
+  return (float)(4294967296.0 / (double)q * (1.0 - 0x1p-20));
+}
+__host__ __device__ inline float quot_factor_lo(uint64_t q) { return (float)(1.0 / (double)q * (1.0 - 0x1p-20)); }
+
 struct Mod {  // per-prime constants
   uint64_t q, q2, q4, nq, nq2, nq4, nq8;  // q, 2q, 4q, and the negatives mod 2^64 of q, 2q, 4q, 8q
+  float fa, fb;                           // quot_factor_hi(q), quot_factor_lo(q)
   __device__ __forceinline__ explicit Mod(uint64_t p)
-      : q(p), q2(p << 1), q4(p << 2), nq(0 - p), nq2(0 - (p << 1)), nq4(0 - (p << 2)), nq8(0 - (p << 3)) {}
+      : q(p), q2(p << 1), q4(p << 2), nq(0 - p), nq2(0 - (p << 1)), nq4(0 - (p << 2)), nq8(0 - (p << 3)),
+        fa(quot_factor_hi(p)), fb(quot_factor_lo(p)) {}
   Mod() = default;
+  // From a per-prime constant row {q, 2q, 4q, -q, -2q, -4q, -8q, f} (negatives mod 2^64), f
+  // holding the bits of quot_factor_hi(q) in its low and quot_factor_lo(q) in its high word.
+  template <typename Ptr>
+  static __device__ __forceinline__ Mod load(Ptr c) {
+    Mod m;
+    m.q = c[0];
+    m.q2 = c[1];
+    m.q4 = c[2];
+    m.nq = c[3];
+    m.nq2 = c[4];
+    m.nq4 = c[5];
+    m.nq8 = c[6];
+    const uint64_t f = c[7];
+    m.fa = __uint_as_float((uint32_t)f);
+    m.fb = __uint_as_float((uint32_t)(f >> 32));
+    return m;
+  }
 };
 
 __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
@@ -204,9 +230,15 @@ struct Arith<true> {
     X = mul(s, n, m);
     Y = mul(d, wn, m);
   }
-  // [0, 16q) -> [0, q)
+  // [0, 16q) -> [0, q).  k = floor(x / q) < 16 is estimated in float from the two halves
+  // of x with the low-biased factors of Mod: every rounding error is far below the 2^-20
+  // bias, so the estimate is k or k - 1, x - estimate * q lies in [0, 2q), and one
+  // conditional subtraction finishes.
   static __device__ __forceinline__ uint64_t fwd_final(uint64_t x, const Mod& m) {
-    return csub_sign(csub_sign(csub_sign(csub_sign(x, m.nq8), m.nq4), m.nq2), m.nq);
+    const float lo = __fmul_rn(__uint2float_rn((uint32_t)x), m.fb);
+    const float e = __fmaf_rn(__uint2float_rn((uint32_t)(x >> 32)), m.fa, lo);
+    const uint32_t k = __float2uint_rz(e);
+    return csub_sign(x + (uint64_t)k * m.nq, m.nq);
   }
   static __device__ __forceinline__ uint64_t inv_final(uint64_t x, const Mod& m) {
     return csub_sign(csub_sign(x, m.nq2), m.nq);

@@ -5,10 +5,17 @@
 //   1. for any b < 2^64 the remainder lies in [0, 4q) and is congruent to b*w mod q;
 //   2. Cooley-Tukey butterflies that reduce X by 8q only in even stages keep values below 16q,
 //      and every conditional subtraction has |x - m| < 2^63 (the sign test is valid);
-//   3. the forward final reduction (8q, 4q, 2q, q) maps [0, 16q) onto [0, q).
+//   3. the forward final reduction (8q, 4q, 2q, q) maps [0, 16q) onto [0, q);
+//   4. so does the quotient-estimate form: k = floor(x / q) estimated in float from the two
+//      32-bit halves of x with factors 2^32/q and 1/q scaled by (1 - 2^-20) before rounding,
+//      then x - k*q (in [0, 2q) when the estimate is k or k - 1) and one subtraction of q.
+//      The float steps (round-to-nearest conversions, a product, a fused multiply-add,
+//      truncation) are IEEE single precision on both the host and the GPU.
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <random>
+#include <vector>
 
 typedef unsigned __int128 u128;
 
@@ -35,8 +42,45 @@ static uint64_t csub(uint64_t x, uint64_t m, uint64_t q) {
   return (int64_t)d < 0 ? x : d;
 }
 
+static uint64_t quotient_final(uint64_t x, uint64_t q) {
+  const float fa = (float)(4294967296.0 / (double)q * (1.0 - 0x1p-20));
+  const float fb = (float)(1.0 / (double)q * (1.0 - 0x1p-20));
+  volatile float lo = (float)(uint32_t)x * fb;   // a separate rounding, as on the GPU
+  const float e = std::fmaf((float)(uint32_t)(x >> 32), fa, lo);
+  const uint32_t k = (uint32_t)e;                // truncation
+  if (k > 15) fail("quotient estimate above 15", q, x, k);
+  const uint64_t r = x - (uint64_t)k * q;        // modulo 2^64
+  if (r >= 2 * q) fail("x - k*q outside [0, 2q)", q, x, k);
+  return csub(r, q, q);
+}
+
+static void check_quotient_final(uint64_t q, uint64_t x) {
+  const uint64_t v = quotient_final(x, q);
+  if (v >= q || v != x % q) fail("quotient final reduction", q, x, v);
+}
+
 int main() {
   std::mt19937_64 g(2012);
+  // claim 4 at every multiple of q below 16q (and just around it), for random and extreme q
+  {
+    std::vector<uint64_t> qs = {3, 5, 7, (1ull << 31) - 1, (1ull << 32) + 15, (1ull << 59) + 1,
+                                (1ull << 59) + 55, (1ull << 60) - 93, (1ull << 60) - 1};
+    for (int i = 0; i < 20000; ++i) {
+      const int bits = 2 + (int)(g() % 59);   // 2..60-bit odd moduli
+      uint64_t q = (g() >> (64 - bits)) | (1ull << (bits - 1)) | 1;
+      if (q >= (1ull << 60)) q = (1ull << 60) - 1;
+      if (q > 2) qs.push_back(q);
+    }
+    for (const uint64_t q : qs) {
+      for (uint64_t k = 0; k <= 16; ++k) {
+        for (int64_t d = -3; d <= 3; ++d) {
+          const __int128 x = (__int128)k * q + d;
+          if (x >= 0 && x < (__int128)16 * q) check_quotient_final(q, (uint64_t)x);
+        }
+      }
+      for (int j = 0; j < 16; ++j) check_quotient_final(q, g() % (16 * q));
+    }
+  }
   for (int trial = 0; trial < 300000; ++trial) {
     const int bits = 30 + (int)(g() % 31);   // 30..60-bit odd moduli (primality is irrelevant here)
     uint64_t q = (g() >> (64 - bits)) | (1ull << (bits - 1)) | 1;
@@ -78,6 +122,7 @@ int main() {
     uint64_t v = X;
     v = csub(v, 8 * q, q); v = csub(v, 4 * q, q); v = csub(v, 2 * q, q); v = csub(v, q, q);
     if (v >= q || v != xr) fail("final reduction", q, X, v);
+    if (quotient_final(X, q) != xr) fail("quotient final reduction", q, X, xr);
   }
   std::printf("%ld failures\n", failures);
   return failures != 0;
