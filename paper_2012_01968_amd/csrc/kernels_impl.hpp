@@ -28,7 +28,11 @@ constexpr int row_lr(int logm) {
 #ifndef NTTK_ROW_PRELOAD
 #define NTTK_ROW_PRELOAD 1
 #endif
-constexpr int kColWidth = NTTK_COL_WIDTH;     // columns per column-pass tile
+constexpr int kColWidth = NTTK_COL_WIDTH;     // columns per column-pass tile (any N2 >= 16)
+#ifndef NTTK_COL_WIDTH_WIDE
+#define NTTK_COL_WIDTH_WIDE 64
+#endif
+constexpr int kColWidthWide = NTTK_COL_WIDTH_WIDE;   // columns per tile when N2 allows it
 constexpr bool kRowPreload = NTTK_ROW_PRELOAD != 0;   // row pass: a step's twiddles loaded up front
 
 template <int R>
@@ -375,24 +379,25 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void mul_row_kernel(PassArgs af, 
 }
 
 // -------------------------------------------------------------------------- column pass
-// kColWidth adjacent columns of one vector per workgroup (the coalesced Kernel-1 of
-// Section VI-C: lanes of a wave cover adjacent columns, so every row segment is one
-// full 128-byte line).  The first N1 twiddles are staged in LDS before use.
+// W adjacent columns of one vector per workgroup (the coalesced Kernel-1 of Section VI-C:
+// lanes of a wave cover adjacent columns, so every row segment is one run of W * 8 bytes).
+// Longer runs stream better from HBM: the launcher takes kColWidthWide columns when N2 has
+// that many and the workgroup stays at 512 lanes or fewer, and kColWidth otherwise.  The first N1 twiddles are staged in LDS before use.
 
-template <int LOGM>
+template <int LOGM, int WREQ = kColWidth>
 struct ColCfg {
   using S = Steps<LOGM, kLR>;
   static constexpr int M = 1 << LOGM;
   static constexpr int T = M / S::R;      // lanes per column
-  static constexpr int W = kColWidth * T > 1024 ? 1024 / T : kColWidth;   // at most 1024 lanes
+  static constexpr int W = WREQ * T > 1024 ? 1024 / T : WREQ;   // at most 1024 lanes
   static constexpr int NT = W * T;
   static constexpr int PITCH = W;         // LDS elements per matrix row
   static __device__ __forceinline__ uint32_t at(uint32_t r) { return r * PITCH; }   // LDS offset of row r
 };
 
-template <bool FAST, int LOGM>
-__global__ __launch_bounds__(ColCfg<LOGM>::NT) void fwd_col_kernel(PassArgs a) {
-  using C = ColCfg<LOGM>;
+template <bool FAST, int LOGM, int WREQ>
+__global__ __launch_bounds__((ColCfg<LOGM, WREQ>::NT)) void fwd_col_kernel(PassArgs a) {
+  using C = ColCfg<LOGM, WREQ>;
   using S = typename C::S;
   __shared__ uint64_t lds[C::M * C::PITCH];
   __shared__ Tw twl[C::M];
@@ -436,10 +441,10 @@ __global__ __launch_bounds__(ColCfg<LOGM>::NT) void fwd_col_kernel(PassArgs a) {
   for (int u = 0; u < S::R; ++u) colp[(size_t)S::template idx<S::K - 1>(t, u) << logN2] = x[u];
 }
 
-template <bool FAST, int LOGM>
-__global__ __launch_bounds__(ColCfg<LOGM>::NT) void inv_col_kernel(PassArgs a) {
+template <bool FAST, int LOGM, int WREQ>
+__global__ __launch_bounds__((ColCfg<LOGM, WREQ>::NT)) void inv_col_kernel(PassArgs a) {
   using A = Arith<FAST>;
-  using C = ColCfg<LOGM>;
+  using C = ColCfg<LOGM, WREQ>;
   using S = typename C::S;
   __shared__ uint64_t lds[C::M * C::PITCH];
   __shared__ Tw twl[C::M];
@@ -502,20 +507,44 @@ hipError_t go_inv_row(const PassArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <bool FAST, int LOGM, int WREQ>
+hipError_t launch_fwd_col(const PassArgs& a, hipStream_t st) {
+  using C = ColCfg<LOGM, WREQ>;
+  const uint64_t blocks = (a.n_vec * ((1u << (a.logN - LOGM)) / C::W) + 7) / 8 * 8;
+  hipLaunchKernelGGL((fwd_col_kernel<FAST, LOGM, WREQ>), dim3((uint32_t)blocks), dim3(C::NT), 0, st, a);
+  return hipGetLastError();
+}
+
+template <bool FAST, int LOGM, int WREQ>
+hipError_t launch_inv_col(const PassArgs& a, hipStream_t st) {
+  using C = ColCfg<LOGM, WREQ>;
+  const uint64_t blocks = (a.n_vec * ((1u << (a.logN - LOGM)) / C::W) + 7) / 8 * 8;
+  hipLaunchKernelGGL((inv_col_kernel<FAST, LOGM, WREQ>), dim3((uint32_t)blocks), dim3(C::NT), 0, st, a);
+  return hipGetLastError();
+}
+
+// The wide tile where N2 = N / N1 holds that many columns, for columns of at most 64 points:
+// the wide tile of longer columns is a 1024-lane workgroup with over 64 KB of LDS, which
+// measured slower than the narrow one.
+template <int LOGM>
+constexpr bool col_wide_differs() {
+  return ColCfg<LOGM, kColWidthWide>::W != ColCfg<LOGM, kColWidth>::W && ColCfg<LOGM, kColWidthWide>::NT <= 512;
+}
+
 template <bool FAST, int LOGM>
 hipError_t go_fwd_col(const PassArgs& a, hipStream_t st) {
-  using C = ColCfg<LOGM>;
-  const uint64_t blocks = (a.n_vec * ((1u << (a.logN - LOGM)) / C::W) + 7) / 8 * 8;
-  hipLaunchKernelGGL((fwd_col_kernel<FAST, LOGM>), dim3((uint32_t)blocks), dim3(C::NT), 0, st, a);
-  return hipGetLastError();
+  if constexpr (col_wide_differs<LOGM>())
+    if ((1u << (a.logN - LOGM)) >= (uint32_t)ColCfg<LOGM, kColWidthWide>::W)
+      return launch_fwd_col<FAST, LOGM, kColWidthWide>(a, st);
+  return launch_fwd_col<FAST, LOGM, kColWidth>(a, st);
 }
 
 template <bool FAST, int LOGM>
 hipError_t go_inv_col(const PassArgs& a, hipStream_t st) {
-  using C = ColCfg<LOGM>;
-  const uint64_t blocks = (a.n_vec * ((1u << (a.logN - LOGM)) / C::W) + 7) / 8 * 8;
-  hipLaunchKernelGGL((inv_col_kernel<FAST, LOGM>), dim3((uint32_t)blocks), dim3(C::NT), 0, st, a);
-  return hipGetLastError();
+  if constexpr (col_wide_differs<LOGM>())
+    if ((1u << (a.logN - LOGM)) >= (uint32_t)ColCfg<LOGM, kColWidthWide>::W)
+      return launch_inv_col<FAST, LOGM, kColWidthWide>(a, st);
+  return launch_inv_col<FAST, LOGM, kColWidth>(a, st);
 }
 
 #define NTTK_ROW_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13)

@@ -86,8 +86,12 @@ def test_ot_small_bases(logN, base):
     check_fwd_inv(1 << logN, 4, 3, 60, 300 + logN, twiddle_mode=ntt.TWIDDLE_OT, ot_stages=2, ot_log2_base=base)
 
 
-@pytest.mark.parametrize("logN,n1", [(13, -1), (13, 4), (13, 9), (14, 4), (14, 10), (15, 5), (16, 4), (16, 6),
-                                     (16, 7), (16, 9), (16, 10), (17, 4), (17, 7), (17, 9), (17, 10)])
+# Columns of up to 64 points take the wide 64-column tile when N2 = N / N1 has 64 columns
+# (exactly one tile per vector at (12, 6)), the 16-column tile otherwise (N2 = 16, 32 at
+# (13, 9), (13, 8); longer columns at (13, 7) and up)
+@pytest.mark.parametrize("logN,n1", [(12, 6), (13, -1), (13, 4), (13, 7), (13, 8), (13, 9), (14, 4), (14, 10),
+                                     (15, 5), (16, 4), (16, 6), (16, 7), (16, 9), (16, 10), (17, 4), (17, 7),
+                                     (17, 9), (17, 10)])
 def test_pass_splits(logN, n1):
     check_fwd_inv(1 << logN, 2, 2, 60, 400 + logN, log2_n1=n1, kernel_path=ntt.PATH_SPLIT)
     check_fwd_inv(1 << logN, 2, 1, 60, 450 + logN, log2_n1=n1, twiddle_mode=ntt.TWIDDLE_OT, ot_stages=2,
