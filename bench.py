@@ -12,7 +12,8 @@ the copies stay valid for the whole run.
 
 Printed (stdout, one JSON line): limb-NTTs/s over the timed steps, the roofline of the
 dominant kernel (algorithmic bytes of one launch / its average duration from HIP events
-on the launch stream), per-step p50/p99, the plain one-call-per-polynomial rate, and the
+on the launch stream), the same kernel's VALU issue utilization (executed instructions from
+the committed counters), per-step p50/p99, the plain one-call-per-polynomial rate, and the
 CPU oracle timed on this host.  Everything else goes to stderr.
 """
 from __future__ import annotations
@@ -32,6 +33,9 @@ if ROOT not in sys.path:
 
 METRIC = "NTTs/s + % HBM roofline at N=2^16×45 limbs; batched vs plain, p99 latency"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+# VALU issue rate: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 32-bit integer instruction per
+# 4 cycles on a 16-lane SIMD
+VALU_ISSUE_PEAK_GINST = 256 * 4 * 2.4 / 4
 WORKLOAD = dict(N=1 << 16, L=45, P=2, bits=60, seed=2)
 
 
@@ -79,8 +83,10 @@ def tune_shape(N: int, primes, polys: int) -> dict:
             "seconds": round(time.perf_counter() - t0, 2)}
 
 
-def read_traffic(kernel: str, src_hash: str, path: str | None = None):
-    """HBM bytes per launch from the committed counter summary, if it matches this source."""
+def read_traffic(kernel: str, src_hash: str, path: str | None = None, field: str = "bytes_per_launch"):
+    """A per-launch counter figure (HBM bytes, or VALU instructions with
+    field="valu_insts_per_launch") from the committed counter summary, if it matches this
+    source."""
     path = path or os.path.join(ROOT, "profiles", "traffic_counters.txt")
     if not os.path.exists(path):
         return None
@@ -93,7 +99,7 @@ def read_traffic(kernel: str, src_hash: str, path: str | None = None):
         rec[k.strip()] = v.strip()
     if rec.get("source_hash") != src_hash:
         return None
-    key = f"bytes_per_launch[{kernel}]"
+    key = f"{field}[{kernel}]"
     return float(rec[key]) if key in rec else None
 
 
@@ -295,6 +301,13 @@ def main() -> int:
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "kernel_us": round(r["kms"][dom] * 1e3, 2), "alg_bytes_per_launch": alg_bytes}
+    # the same kernel against the VALU issue rate: executed instructions from the counters
+    valu = read_traffic(f"{variant_key(info, ots)}:{dom}", src_hash, field="valu_insts_per_launch")
+    valu_issue = None
+    if valu is not None:
+        ginst = valu / (r["kms"][dom] * 1e-3) / 1e9
+        valu_issue = {"kernel": dom, "insts_per_launch": int(valu), "achieved_ginst_s": round(ginst, 1),
+                      "peak_ginst_s": VALU_ISSUE_PEAK_GINST, "frac": round(ginst / VALU_ISSUE_PEAK_GINST, 4)}
     step_bytes = 2 * sum(16 * P * L * N + twiddle_bytes(k, N, L, info["log2_n1"], ots)
                          for k in (["col", "row"] if info["log2_n1"] else ["row"]))
     step_frac = step_bytes / (r["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS
@@ -322,6 +335,7 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "step_hbm_frac": round(step_frac, 4),
+        "valu_issue": valu_issue,
         "p50_ms": round(float(np.percentile(r["per"], 50)), 5),
         "p99_ms": round(float(np.percentile(r["per"], 99)), 5),
         "plain_value": round(n_limb_ntts / (r["plain_ms"] * 1e-3), 1),

@@ -19,6 +19,9 @@ def test_traffic_lookup(tmp_path):
     assert b.read_traffic("table-split-n1=8:fwd_row", "abc", str(f)) == 146540105.0
     assert b.read_traffic("table-split-n1=8:inv_row", "abc", str(f)) is None
     assert b.read_traffic("table-split-n1=8:fwd_row", "other", str(f)) is None   # stale counters
+    f.write_text("source_hash: abc\nvalu_insts_per_launch[table-split-n1=6:inv_row]: 11554560\n")
+    assert b.read_traffic("table-split-n1=6:inv_row", "abc", str(f), field="valu_insts_per_launch") == 11554560.0
+    assert b.read_traffic("table-split-n1=6:inv_row", "abc", str(f)) is None
 
 
 def test_committed_traffic_covers_its_configuration():
