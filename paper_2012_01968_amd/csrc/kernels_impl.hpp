@@ -269,8 +269,10 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void inv_row_kernel(PassArgs a) {
 #pragma unroll
       for (int u = 0; u < S::R; ++u) x[u] = l[C::at(S::template idx<k>(t, u))];
     }
-    if constexpr (kRowPreload) gs_step<FAST, LOGM, C::LR, k, OTS, SCALE0>(x, t, base, tabfn, ot, md, sc0, sc1, pre);
-    else gs_step<FAST, LOGM, C::LR, k, OTS, SCALE0>(x, t, base, tabfn, ot, md, sc0, sc1);
+    // the first register step sees the caller's canonical input
+    constexpr int IN_B = k == S::K - 1 ? 1 : 8;
+    if constexpr (kRowPreload) gs_step<FAST, LOGM, C::LR, k, OTS, SCALE0, IN_B>(x, t, base, tabfn, ot, md, sc0, sc1, pre);
+    else gs_step<FAST, LOGM, C::LR, k, OTS, SCALE0, IN_B>(x, t, base, tabfn, ot, md, sc0, sc1);
   });
 
   if constexpr (SCALE0) {
@@ -366,7 +368,8 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void mul_row_kernel(PassArgs af, 
 #pragma unroll
       for (int u = 0; u < S::R; ++u) x[u] = l[C::at(S::template idx<k>(t, u))];
     }
-    gs_step<FAST, LOGM, C::LR, k, OTS, SCALE0>(x, t, base, tabfni, oti, md, sc0, sc1, pre);
+    // the key product leaves canonical values (padding rows skip it, but are never stored)
+    gs_step<FAST, LOGM, C::LR, k, OTS, SCALE0, k == S::K - 1 ? 1 : 8>(x, t, base, tabfni, oti, md, sc0, sc1, pre);
   });
   if constexpr (SCALE0) {
 #pragma unroll

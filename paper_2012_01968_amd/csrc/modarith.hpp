@@ -43,10 +43,10 @@ __host__ __device__ inline float quot_factor_hi(uint64_t q) {
 __host__ __device__ inline float quot_factor_lo(uint64_t q) { return (float)(1.0 / (double)q * (1.0 - 0x1p-20)); }
 
 struct Mod {  // per-prime constants
-  uint64_t q, q2, q4, nq, nq2, nq4, nq8;  // q, 2q, 4q, and the negatives mod 2^64 of q, 2q, 4q, 8q
+  uint64_t q, q2, q4, q8, nq, nq2, nq4, nq8;  // q, 2q, 4q, 8q, and the negatives mod 2^64 of q, 2q, 4q, 8q
   float fa, fb;                           // quot_factor_hi(q), quot_factor_lo(q)
   __device__ __forceinline__ explicit Mod(uint64_t p)
-      : q(p), q2(p << 1), q4(p << 2), nq(0 - p), nq2(0 - (p << 1)), nq4(0 - (p << 2)), nq8(0 - (p << 3)),
+      : q(p), q2(p << 1), q4(p << 2), q8(p << 3), nq(0 - p), nq2(0 - (p << 1)), nq4(0 - (p << 2)), nq8(0 - (p << 3)),
         fa(quot_factor_hi(p)), fb(quot_factor_lo(p)) {}
   Mod() = default;
   // From a per-prime constant row {q, 2q, 4q, -q, -2q, -4q, -8q, f} (negatives mod 2^64), f
@@ -57,6 +57,7 @@ struct Mod {  // per-prime constants
     m.q = c[0];
     m.q2 = c[1];
     m.q4 = c[2];
+    m.q8 = m.q4 + m.q4;
     m.nq = c[3];
     m.nq2 = c[4];
     m.nq4 = c[5];
@@ -209,24 +210,25 @@ struct Arith<true> {
     X = x + v;
     Y = x + m.q4 - v;
   }
-  // Gentleman-Sande: X, Y in [0, 4q) -> X + Y, (X - Y) W in [0, 4q).
+  // Gentleman-Sande: X, Y in [0, 8q) -> X + Y in [0, 8q), (X - Y) W in [0, 4q).  (gs_step
+  // tracks tighter bounds per register and skips reductions these forms always make.)
   static __device__ __forceinline__ void gs(uint64_t& X, uint64_t& Y, const Tw& t, const Mod& m) {
-    const uint64_t s = csub_sign(X + Y, m.nq4);
-    const uint64_t d = X + m.q4 - Y;
+    const uint64_t s = csub_sign(X + Y, m.nq8);
+    const uint64_t d = X + m.q8 - Y;
     X = s;
     Y = mul(d, t, m);
   }
   static __device__ __forceinline__ void gs2(uint64_t& X, uint64_t& Y, const Tw& a, const Tw& b, const Mod& m) {
-    const uint64_t s = csub_sign(X + Y, m.nq4);
-    const uint64_t d = X + m.q4 - Y;
+    const uint64_t s = csub_sign(X + Y, m.nq8);
+    const uint64_t d = X + m.q8 - Y;
     X = s;
     Y = mul(mul(d, a, m), b, m);
   }
-  // Stage 0 of a single-pass inverse, with the 1/N scale: X, Y in [0, 4q) -> [0, 4q).
+  // Stage 0 of the whole inverse, with the 1/N scale: X, Y in [0, 8q) -> [0, 4q).
   static __device__ __forceinline__ void gs_scaled(uint64_t& X, uint64_t& Y, const Tw& wn, const Tw& n,
                                                    const Mod& m) {
     const uint64_t s = X + Y;
-    const uint64_t d = X + m.q4 - Y;
+    const uint64_t d = X + m.q8 - Y;
     X = mul(s, n, m);
     Y = mul(d, wn, m);
   }

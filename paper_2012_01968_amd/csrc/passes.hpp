@@ -241,9 +241,28 @@ __device__ __forceinline__ void ct_step(uint64_t (&x)[NR], uint32_t t, uint32_t 
 }
 
 // Inverse (Gentleman-Sande) register step K_STEP: stages from the low bit up.
+// Value bounds of the fast Gentleman-Sande stages, in multiples of q.  The register step's
+// inputs lie below IN_B q (IN_B <= 8).  In the local stage i of a step, register u (bit i
+// clear) pairs with u | 2^i; both played the same part in the stage before (bit i-1 of u),
+// so they share a bound.  A product is below 4q whatever it multiplied; a sum doubles the
+// bound and is reduced by 8q only when that would pass 8q.  So a sum of two products needs
+// no reduction, and everything stays below 8q.
+template <int IN_B>
+struct GsRange {
+  static_assert(IN_B >= 1 && IN_B <= 8, "Gentleman-Sande inputs must lie below 8q");
+  // bound of register u before local stage i
+  static constexpr int before(int i, int u) {
+    int b = IN_B;
+    for (int j = 0; j < i; ++j) b = (u >> j) & 1 ? 4 : (2 * b > 8 ? 8 : 2 * b);
+    return b;
+  }
+  static constexpr bool reduce(int i, int u) { return 2 * before(i, u) > 8; }
+};
+
 // SCALE0: this sub-transform holds stage 0 of the whole transform, whose butterfly
 // also applies the 1/N scale (sc0 = 1/N, sc1 = Psi_inv[1]/N).
-template <bool FAST, int LOGM, int LR, int K_STEP, int OTS, bool SCALE0, int NR, typename TabFn,
+// IN_B: the step's inputs lie below IN_B q (fast policy; 1 for canonical inputs).
+template <bool FAST, int LOGM, int LR, int K_STEP, int OTS, bool SCALE0, int IN_B = 8, int NR, typename TabFn,
           typename Pre = NoTw>
 __device__ __forceinline__ void gs_step(uint64_t (&x)[NR], uint32_t t, uint32_t base,
                                         TabFn&& tab, const OtTables& ot, const Mod& md,
@@ -280,8 +299,9 @@ __device__ __forceinline__ void gs_step(uint64_t (&x)[NR], uint32_t t, uint32_t 
       for (int k = 0; k < H; ++k) {
         const int u = ((k >> i) << (i + 1)) | (k & ((1 << i) - 1));
         const uint64_t X = x[u], Y = x[u | (1 << i)];
-        ds[k] = X + md.q4 - Y;
-        x[u] = csub_sign(X + Y, md.nq4);
+        const int b = GsRange<IN_B>::before(i, u);   // folded: i and (after unrolling) u are constants
+        ds[k] = X + (b == 1 ? md.q : b == 2 ? md.q2 : b == 4 ? md.q4 : md.q8) - Y;
+        x[u] = GsRange<IN_B>::reduce(i, u) ? csub_sign(X + Y, md.nq8) : X + Y;
       }
       A::template mul_n<H>(v, ds, w, md);
       if constexpr (OTS > 0 && s >= LOGM - OTS) A::template mul_n<H>(v, v, w2, md);

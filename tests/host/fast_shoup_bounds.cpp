@@ -10,11 +10,17 @@
 //      32-bit halves of x with factors 2^32/q and 1/q scaled by (1 - 2^-20) before rounding,
 //      then x - k*q (in [0, 2q) when the estimate is k or k - 1) and one subtraction of q.
 //      The float steps (round-to-nearest conversions, a product, a fused multiply-add,
-//      truncation) are IEEE single precision on both the host and the GPU.
+//      truncation) are IEEE single precision on both the host and the GPU;
+//   5. Gentleman-Sande register steps (8 values, up to 3 stages) with per-register bounds:
+//      inputs below IN_B q, a sum reduced by 8q only when its inputs' bound is above 4q, the
+//      difference offset by the inputs' bound, products below 4q; every value stays below 8q,
+//      and a chain of steps ending in the scaled stage and the final reduction is canonical
+//      and congruent to the exact transform's arithmetic.
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <random>
+#include <utility>
 #include <vector>
 
 typedef unsigned __int128 u128;
@@ -59,8 +65,72 @@ static void check_quotient_final(uint64_t q, uint64_t x) {
   if (v >= q || v != x % q) fail("quotient final reduction", q, x, v);
 }
 
+// bound (in q) of register u before local stage i of a step whose inputs lie below in_b q
+static int gs_before(int in_b, int i, int u) {
+  int b = in_b;
+  for (int j = 0; j < i; ++j) b = (u >> j) & 1 ? 4 : (2 * b > 8 ? 8 : 2 * b);
+  return b;
+}
+
+// one step of nb stages on x[8] (values) and r[8] (their exact residues)
+static void gs_register_step(uint64_t* x, uint64_t* r, int in_b, int nb, uint64_t q, std::mt19937_64& g) {
+  for (int i = 0; i < nb; ++i) {
+    const uint64_t w = g() % q, wb = (uint64_t)(((u128)w << 64) / q);
+    for (int u = 0; u < 8; ++u) {
+      if (u & (1 << i)) continue;
+      const int v = u | (1 << i);
+      const int b = gs_before(in_b, i, u);
+      if (x[u] >= (uint64_t)b * q || x[v] >= (uint64_t)b * q) fail("GS input above its bound", q, x[u], x[v]);
+      const uint64_t sum = x[u] + x[v];
+      const uint64_t s = 2 * b > 8 ? csub(sum, 8 * q, q) : sum;
+      const uint64_t d = x[u] + (uint64_t)b * q - x[v];
+      const uint64_t p = fast_mul(d, w, wb, q);
+      if (s >= 8 * q) fail("GS sum >= 8q", q, x[u], x[v]);
+      if (p >= 4 * q) fail("GS product >= 4q", q, d, w);
+      const uint64_t rs = (r[u] + r[v]) % q, rp = mulmod((r[u] + q - r[v]) % q, w, q);
+      if (s % q != rs || p % q != rp) fail("GS not congruent", q, s, p);
+      x[u] = s; r[u] = rs; x[v] = p; r[v] = rp;
+    }
+  }
+}
+
 int main() {
   std::mt19937_64 g(2012);
+  // claim 5: chains of Gentleman-Sande register steps, inputs pushed to the top of their bounds
+  for (int trial = 0; trial < 100000; ++trial) {
+    const int bits = 40 + (int)(g() % 21);
+    uint64_t q = (g() >> (64 - bits)) | (1ull << (bits - 1)) | 1;
+    if (q >= (1ull << 60)) q = (1ull << 60) - 1;
+    uint64_t x[8], r[8];
+    for (int u = 0; u < 8; ++u) {   // canonical input, half of it at q - 1
+      x[u] = (g() & 1) ? q - 1 - (g() & 3) : g() % q;
+      r[u] = x[u];
+    }
+    const int steps = 1 + (int)(g() % 4);
+    for (int k = 0; k < steps; ++k) {
+      gs_register_step(x, r, k == 0 ? 1 : 8, 1 + (int)(g() % 3), q, g);
+      // between steps the values are permuted across registers (the LDS exchange); push some
+      // to the top of the next step's input range, keeping them congruent
+      for (int u = 7; u > 0; --u) {
+        const int v = (int)(g() % (u + 1));
+        std::swap(x[u], x[v]);
+        std::swap(r[u], r[v]);
+      }
+      for (int u = 0; u < 8; ++u)
+        if (g() % 4 == 0) x[u] = r[u] + q * ((8 * q - 1 - r[u]) / q);   // largest value below 8q
+    }
+    // the scaled last stage and the final reduction
+    const uint64_t n = g() % q, nb = (uint64_t)(((u128)n << 64) / q);
+    const uint64_t wn = g() % q, wnb = (uint64_t)(((u128)wn << 64) / q);
+    for (int u = 0; u < 8; u += 2) {
+      const uint64_t s = x[u] + x[u + 1], d = x[u] + 8 * q - x[u + 1];
+      const uint64_t a = fast_mul(s, n, nb, q), b = fast_mul(d, wn, wnb, q);
+      if (a >= 4 * q || b >= 4 * q) fail("scaled stage output >= 4q", q, a, b);
+      const uint64_t ca = csub(csub(a, 2 * q, q), q, q), cb = csub(csub(b, 2 * q, q), q, q);
+      const uint64_t ra = mulmod((r[u] + r[u + 1]) % q, n, q), rb = mulmod((r[u] + q - r[u + 1]) % q, wn, q);
+      if (ca != ra || cb != rb) fail("scaled stage / final reduction", q, ca, cb);
+    }
+  }
   // claim 4 at every multiple of q below 16q (and just around it), for random and extreme q
   {
     std::vector<uint64_t> qs = {3, 5, 7, (1ull << 31) - 1, (1ull << 32) + 15, (1ull << 59) + 1,
