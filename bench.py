@@ -153,6 +153,9 @@ def main() -> int:
                     help="arrival rate of a second, 5-second stream above the per-request path's capacity (0 skips)")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch section")
     ap.add_argument("--no-polymul", action="store_true", help="skip the large-parameter product section")
+    ap.add_argument("--profile-polymul", action="store_true",
+                    help="counter-collection driver for the product workload: --steps products with one "
+                         "twiddle mode (--variant, --log2-n1), then one plain device copy of an operand")
     ap.add_argument("--profile-run", action="store_true",
                     help="counter-collection driver: --steps steps of one twiddle mode (no timing, no JSON), "
                          "then one plain device copy of a ciphertext for the counters' byte calibration")
@@ -180,6 +183,8 @@ def main() -> int:
     log(f"workload N={N} L={L} P={P}: {ct_bytes/1e6:.1f} MB per ciphertext, {R} rotating copies "
         f"({R*ct_bytes/2**30:.2f} GiB)")
 
+    if args.profile_polymul:
+        return polymul_profile_run(args)
     if args.profile_run:
         mode = "ot-fused" if args.variant == "auto" else args.variant
         plan = ntt.ntt_plan_create(N, primes, log2_n1=args.log2_n1, **VARIANTS[mode])
@@ -353,6 +358,32 @@ def main() -> int:
 
 
 POLYMUL = dict(logN=17, L=60, polys=2, bits=60, seed=3)
+
+
+def polymul_profile_run(args) -> int:
+    """Counter driver for the product workload: `args.steps` products c = a * b with one named
+    plan, then one plain device copy of an operand (its bytes calibrate the counters)."""
+    import torch
+    import synth
+    import paper_2012_01968_amd as ntt
+
+    cfg = POLYMUL
+    N, L, P = 1 << cfg["logN"], cfg["L"], cfg["polys"]
+    primes = synth.gen_primes(cfg["seed"], N, cfg["bits"], L)
+    host = synth.residue_batch(cfg["seed"], primes, N, 2 * P)
+    da = torch.from_numpy(np.ascontiguousarray(host[:P]).view(np.int64)).to("cuda")
+    db = torch.from_numpy(np.ascontiguousarray(host[P:]).view(np.int64)).to("cuda")
+    dc = torch.empty_like(da)
+    mode = "table-split" if args.variant in ("auto", "tuned") else args.variant
+    plan = ntt.ntt_plan_create(N, primes, log2_n1=args.log2_n1, **VARIANTS[mode])
+    for _ in range(args.steps):
+        ntt.ntt_polymul_negacyclic(plan, da, db, dc)
+    torch.cuda.synchronize()
+    dc.copy_(da)                     # calibration: one plain copy of P*L*N*8 bytes each way
+    torch.cuda.synchronize()
+    plan.destroy()
+    log(f"profile run: {args.steps} products ({mode}, log2_n1={args.log2_n1}) + one {da.numel() * 8}-byte copy")
+    return 0
 
 
 def polymul_bench(args):
