@@ -166,12 +166,16 @@ def test_prime_widths(bits):
     check_fwd_inv(1 << 12, 3, 2, bits, 520 + bits, twiddle_mode=ntt.TWIDDLE_OT, ot_stages=2)
 
 
-@pytest.mark.parametrize("logN", [12, 16])
-def test_extreme_inputs(logN):
+# 62-bit primes take the exact-quotient arithmetic, 60-bit ones the estimated quotient with its
+# lazy ranges (float quotient in the forward final reduction, per-register inverse bounds)
+@pytest.mark.parametrize("logN,bits,opts", [
+    (12, 62, {}), (16, 62, {}), (12, 60, {}), (16, 60, {}), (16, 60, dict(log2_n1=6)),
+    (16, 60, dict(log2_n1=6, twiddle_mode=ntt.TWIDDLE_OT, ot_stages=2)), (17, 60, dict(log2_n1=7))])
+def test_extreme_inputs(logN, bits, opts):
     N = 1 << logN
-    primes = synth.gen_primes(600, N, 62, 2)
+    primes = synth.gen_primes(600, N, bits, 2)
     psis = oracle.roots(primes, N)
-    plan = ntt.ntt_plan_create(N, primes)
+    plan = ntt.ntt_plan_create(N, primes, **opts)
     try:
         zeros = np.zeros((1, 2, N), dtype=np.uint64)
         assert not run_fwd(plan, zeros).any()
