@@ -169,6 +169,15 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void fwd_row_kernel(PassArgs a) {
     ot.b = a.ot_log2_base;
   }
   auto tabfn = [&](uint32_t ix) { return tab[ix]; };
+  // the first register step's twiddles are the same for every lane of a row: with one row per
+  // workgroup they come through scalar loads
+  auto tabu = [&](uint32_t ix) {
+    const cu64* p = (const cu64*)tab + 2 * (size_t)ix;
+    Tw w;
+    w.w = p[0];
+    w.wb = p[1];
+    return w;
+  };
   gu64* rowp = rr.rowp;
   uint64_t* l = lds + v * C::PITCH;
 
@@ -184,7 +193,13 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void fwd_row_kernel(PassArgs a) {
   static_for<0, S::K>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     PreTw<S::R> pre;   // issued before the exchange so the loads overlap the barrier
-    if constexpr (kRowPreload) load_step_twiddles<LOGM, C::LR, k, OTS>(pre.w, pre.w2, t, base, tabfn, ot);
+    if constexpr (kRowPreload) {
+      // (step 0's twiddle index does not depend on the lane: its bits all lie below the step;
+      // with one row per workgroup the row base is the same in every lane)
+      if constexpr (k == 0 && C::V == 1)
+        load_step_twiddles<LOGM, C::LR, k, OTS>(pre.w, pre.w2, 0u, __builtin_amdgcn_readfirstlane(base), tabu, ot);
+      else load_step_twiddles<LOGM, C::LR, k, OTS>(pre.w, pre.w2, t, base, tabfn, ot);
+    }
     if constexpr (k > 0) {
 #pragma unroll
       for (int u = 0; u < S::R; ++u) l[C::at(S::template idx<k - 1>(t, u))] = x[u];
@@ -241,6 +256,15 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void inv_row_kernel(PassArgs a) {
     sc1 = a.scale[2 * limb + 1];
   }
   auto tabfn = [&](uint32_t ix) { return tab[ix]; };
+  // the first register step's twiddles are the same for every lane of a row: with one row per
+  // workgroup they come through scalar loads
+  auto tabu = [&](uint32_t ix) {
+    const cu64* p = (const cu64*)tab + 2 * (size_t)ix;
+    Tw w;
+    w.w = p[0];
+    w.wb = p[1];
+    return w;
+  };
   gu64* rowp = rr.rowp;
   uint64_t* l = lds + v * C::PITCH;
 
@@ -259,7 +283,13 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void inv_row_kernel(PassArgs a) {
   static_for_down<S::K, 0>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     PreTw<S::R> pre;   // issued before the exchange so the loads overlap the barrier
-    if constexpr (kRowPreload) load_step_twiddles<LOGM, C::LR, k, OTS>(pre.w, pre.w2, t, base, tabfn, ot);
+    if constexpr (kRowPreload) {
+      // (step 0's twiddle index does not depend on the lane: its bits all lie below the step;
+      // with one row per workgroup the row base is the same in every lane)
+      if constexpr (k == 0 && C::V == 1)
+        load_step_twiddles<LOGM, C::LR, k, OTS>(pre.w, pre.w2, 0u, __builtin_amdgcn_readfirstlane(base), tabu, ot);
+      else load_step_twiddles<LOGM, C::LR, k, OTS>(pre.w, pre.w2, t, base, tabfn, ot);
+    }
     if constexpr (k < S::K - 1) {
 #pragma unroll
       for (int u = 0; u < S::R; ++u) l[C::at(S::template idx<k + 1>(t, u))] = x[u];
@@ -322,6 +352,16 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void mul_row_kernel(PassArgs af, 
   }
   auto tabfnf = [&](uint32_t ix) { return tabf[ix]; };
   auto tabfni = [&](uint32_t ix) { return tabi[ix]; };
+  // step 0's twiddles through scalar loads when a workgroup holds one row (see fwd_row_kernel)
+  auto scalar_tw = [](const Tw* tab, uint32_t ix) {
+    const cu64* p = (const cu64*)tab + 2 * (size_t)ix;
+    Tw w;
+    w.w = p[0];
+    w.wb = p[1];
+    return w;
+  };
+  auto tabuf = [&](uint32_t ix) { return scalar_tw(tabf, ix); };
+  auto tabui = [&](uint32_t ix) { return scalar_tw(tabi, ix); };
   uint64_t* l = lds + v * C::PITCH;
 
   uint64_t x[S::R];
@@ -335,7 +375,10 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void mul_row_kernel(PassArgs af, 
   static_for<0, S::K>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     PreTw<S::R> pre;
-    load_step_twiddles<LOGM, C::LR, k, OTS>(pre.w, pre.w2, t, base, tabfnf, otf);
+    if constexpr (k == 0 && C::V == 1)
+      load_step_twiddles<LOGM, C::LR, k, OTS>(pre.w, pre.w2, 0u, __builtin_amdgcn_readfirstlane(base), tabuf, otf);
+    else
+      load_step_twiddles<LOGM, C::LR, k, OTS>(pre.w, pre.w2, t, base, tabfnf, otf);
     if constexpr (k > 0) {
 #pragma unroll
       for (int u = 0; u < S::R; ++u) l[C::at(S::template idx<k - 1>(t, u))] = x[u];
@@ -356,7 +399,10 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void mul_row_kernel(PassArgs af, 
   static_for_down<S::K, 0>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     PreTw<S::R> pre;
-    load_step_twiddles<LOGM, C::LR, k, OTS>(pre.w, pre.w2, t, base, tabfni, oti);
+    if constexpr (k == 0 && C::V == 1)
+      load_step_twiddles<LOGM, C::LR, k, OTS>(pre.w, pre.w2, 0u, __builtin_amdgcn_readfirstlane(base), tabui, oti);
+    else
+      load_step_twiddles<LOGM, C::LR, k, OTS>(pre.w, pre.w2, t, base, tabfni, oti);
     if constexpr (k < S::K - 1) {
       // the first of these writes goes to the slots this lane read in the forward half's
       // last exchange, which no other lane reads, so it needs no barrier before it
