@@ -170,7 +170,7 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void fwd_row_kernel(PassArgs a) {
   }
   auto tabfn = [&](uint32_t ix) { return tab[ix]; };
   // the first register step's twiddles are the same for every lane of a row: with one row per
-  // workgroup they come through scalar loads
+  // wave (or fewer) they come through scalar loads
   auto tabu = [&](uint32_t ix) {
     const cu64* p = (const cu64*)tab + 2 * (size_t)ix;
     Tw w;
@@ -195,8 +195,8 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void fwd_row_kernel(PassArgs a) {
     PreTw<S::R> pre;   // issued before the exchange so the loads overlap the barrier
     if constexpr (kRowPreload) {
       // (step 0's twiddle index does not depend on the lane: its bits all lie below the step;
-      // with one row per workgroup the row base is the same in every lane)
-      if constexpr (k == 0 && C::V == 1)
+      // with one row per wave the row base is the same in every lane of the wave)
+      if constexpr (k == 0 && C::T >= 64)
         load_step_twiddles<LOGM, C::LR, k, OTS>(pre.w, pre.w2, 0u, __builtin_amdgcn_readfirstlane(base), tabu, ot);
       else load_step_twiddles<LOGM, C::LR, k, OTS>(pre.w, pre.w2, t, base, tabfn, ot);
     }
@@ -215,16 +215,31 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void fwd_row_kernel(PassArgs a) {
   for (int u = 0; u < S::R; ++u) x[u] = A::fwd_final(x[u], md);
   // back to natural positions through LDS, so that each store instruction writes whole lines
   // (storing each lane's 8 consecutive elements directly measured 7% slower: partial lines)
-  if constexpr (S::K > 1) {
+  if constexpr (S::K > 1 && C::T >= 64 && C::LR == 3) {
+    // A wave holds 512 consecutive elements of its row (8 per lane), so it transposes them
+    // through its own part of the row's LDS slots and needs no barrier: since the last
+    // exchange's barrier every wave only touches its own part.
+    const uint32_t wbase = (t & ~63u) * 8u, lane = t & 63u;
 #pragma unroll
     for (int u = 0; u < S::R; ++u) l[C::at(S::template idx<S::K - 1>(t, u))] = x[u];
-    __syncthreads();
 #pragma unroll
-    for (int u = 0; u < S::R; ++u) x[u] = l[C::at(S::template idx<0>(t, u))];
-  }
-  if (valid) {
+    for (int u = 0; u < S::R; ++u) x[u] = l[C::at(wbase + 64u * u + lane)];
+    if (valid) {
 #pragma unroll
-    for (int u = 0; u < S::R; ++u) rowp[S::template idx<0>(t, u)] = x[u];
+      for (int u = 0; u < S::R; ++u) rowp[wbase + 64u * u + lane] = x[u];
+    }
+  } else {
+    if constexpr (S::K > 1) {
+#pragma unroll
+      for (int u = 0; u < S::R; ++u) l[C::at(S::template idx<S::K - 1>(t, u))] = x[u];
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < S::R; ++u) x[u] = l[C::at(S::template idx<0>(t, u))];
+    }
+    if (valid) {
+#pragma unroll
+      for (int u = 0; u < S::R; ++u) rowp[S::template idx<0>(t, u)] = x[u];
+    }
   }
 }
 
@@ -257,7 +272,7 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void inv_row_kernel(PassArgs a) {
   }
   auto tabfn = [&](uint32_t ix) { return tab[ix]; };
   // the first register step's twiddles are the same for every lane of a row: with one row per
-  // workgroup they come through scalar loads
+  // wave (or fewer) they come through scalar loads
   auto tabu = [&](uint32_t ix) {
     const cu64* p = (const cu64*)tab + 2 * (size_t)ix;
     Tw w;
@@ -285,8 +300,8 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void inv_row_kernel(PassArgs a) {
     PreTw<S::R> pre;   // issued before the exchange so the loads overlap the barrier
     if constexpr (kRowPreload) {
       // (step 0's twiddle index does not depend on the lane: its bits all lie below the step;
-      // with one row per workgroup the row base is the same in every lane)
-      if constexpr (k == 0 && C::V == 1)
+      // with one row per wave the row base is the same in every lane of the wave)
+      if constexpr (k == 0 && C::T >= 64)
         load_step_twiddles<LOGM, C::LR, k, OTS>(pre.w, pre.w2, 0u, __builtin_amdgcn_readfirstlane(base), tabu, ot);
       else load_step_twiddles<LOGM, C::LR, k, OTS>(pre.w, pre.w2, t, base, tabfn, ot);
     }
@@ -352,7 +367,7 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void mul_row_kernel(PassArgs af, 
   }
   auto tabfnf = [&](uint32_t ix) { return tabf[ix]; };
   auto tabfni = [&](uint32_t ix) { return tabi[ix]; };
-  // step 0's twiddles through scalar loads when a workgroup holds one row (see fwd_row_kernel)
+  // step 0's twiddles through scalar loads when a wave holds one row (see fwd_row_kernel)
   auto scalar_tw = [](const Tw* tab, uint32_t ix) {
     const cu64* p = (const cu64*)tab + 2 * (size_t)ix;
     Tw w;
@@ -375,7 +390,7 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void mul_row_kernel(PassArgs af, 
   static_for<0, S::K>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     PreTw<S::R> pre;
-    if constexpr (k == 0 && C::V == 1)
+    if constexpr (k == 0 && C::T >= 64)
       load_step_twiddles<LOGM, C::LR, k, OTS>(pre.w, pre.w2, 0u, __builtin_amdgcn_readfirstlane(base), tabuf, otf);
     else
       load_step_twiddles<LOGM, C::LR, k, OTS>(pre.w, pre.w2, t, base, tabfnf, otf);
@@ -399,7 +414,7 @@ __global__ __launch_bounds__(RowCfg<LOGM>::NT) void mul_row_kernel(PassArgs af, 
   static_for_down<S::K, 0>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     PreTw<S::R> pre;
-    if constexpr (k == 0 && C::V == 1)
+    if constexpr (k == 0 && C::T >= 64)
       load_step_twiddles<LOGM, C::LR, k, OTS>(pre.w, pre.w2, 0u, __builtin_amdgcn_readfirstlane(base), tabui, oti);
     else
       load_step_twiddles<LOGM, C::LR, k, OTS>(pre.w, pre.w2, t, base, tabfni, oti);
