@@ -187,7 +187,16 @@ def main() -> int:
         return polymul_profile_run(args)
     if args.profile_run:
         mode = "ot-fused" if args.variant == "auto" else args.variant
-        plan = ntt.ntt_plan_create(N, primes, log2_n1=args.log2_n1, **VARIANTS[mode])
+        if mode == "tuned":
+            # the tuner's cached plan for this shape, as the timed run would take it (no tuning here)
+            from paper_2012_01968_amd import autotune
+            entry = autotune.lookup(N, primes, P)
+            if entry is None:
+                log("profile run: no cached tuned plan for this shape and kernel build")
+                return 1
+            plan = ntt.ntt_plan_create(N, primes, **entry["opts"])
+        else:
+            plan = ntt.ntt_plan_create(N, primes, log2_n1=args.log2_n1, **VARIANTS[mode])
         for i in range(args.steps):
             ntt.ntt_forward(plan, bufs[i % R])
             ntt.ntt_inverse(plan, bufs[i % R])
