@@ -58,3 +58,18 @@ def test_cache_round_trip(tmp_path):
 def test_source_hash_tracks_the_kernel_sources():
     h = at.source_hash()
     assert len(h) == 16 and h == at.source_hash()
+
+
+def test_committed_cache_holds_the_headline_shape():
+    """The shipped cache has a plan for N=2^16, L=45 (60-bit primes), 2 polys on a 256-CU gfx950
+    for the kernel sources as they stand, so the measurement and its full-size parity test use
+    that plan instead of tuning anew."""
+    import synth
+    primes = synth.gen_primes(2, 1 << 16, 60, 45)
+    with open(at.cache_path()) as f:
+        entries = json.load(f)["entries"]
+    key = at._key("gfx950:256CU", 1 << 16, primes, 2)
+    assert key in entries, "tune cache is stale for the current kernel sources"
+    assert at.source_hash() in key
+    opts = entries[key]["opts"]
+    assert opts in at.candidates(1 << 16)

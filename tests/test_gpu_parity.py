@@ -299,6 +299,58 @@ def test_config2_full(mode):
         plan.destroy()
 
 
+def _bench_module():
+    import importlib.util
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_config2_bench_plans():
+    """Every plan the headline measurement times, built as it builds them, on its own inputs
+    (N=2^16, L=45, 2 polys): the four named variants at the default split and the tuner's cached
+    plan for the shape.  Each is driven the three ways the measurement drives it (one call per
+    step, one call per pass, one call per polynomial) and checked against one oracle forward."""
+    b = _bench_module()
+    W = b.WORKLOAD
+    N, L, P = W["N"], W["L"], W["P"]
+    primes = synth.gen_primes(W["seed"], N, W["bits"], L)
+    data = synth.residue_batch(W["seed"], primes, N, P)
+    psis = oracle.roots(primes, N)
+    want = oracle.forward(data, primes, psis, THREADS)
+    plans = {name: dict(opts, log2_n1=0) for name, opts in b.VARIANTS.items()}
+    from paper_2012_01968_amd import autotune
+    entry = autotune.lookup(N, primes, P)
+    if entry is not None:        # present whenever the cache was refreshed for these kernel sources
+        plans["tuned"] = entry["opts"]
+    for name, opts in plans.items():
+        plan = ntt.ntt_plan_create(N, primes, **opts)
+        try:
+            assert ntt.ntt_plan_get_roots(plan) == psis
+            d = dev(data)
+            ntt.ntt_forward(plan, d)
+            torch.cuda.synchronize()
+            assert np.array_equal(host(d), want), f"{name}: forward"
+            ntt.ntt_inverse(plan, d)
+            torch.cuda.synchronize()
+            assert np.array_equal(host(d), data), f"{name}: inverse(forward)"
+            npass = ntt.ntt_plan_num_passes(plan)
+            for p in range(npass):
+                ntt.ntt_forward_pass(plan, d, p)
+            torch.cuda.synchronize()
+            assert np.array_equal(host(d), want), f"{name}: forward by passes"
+            for p in range(npass):
+                ntt.ntt_inverse_pass(plan, d, p)
+            for i in range(P):
+                ntt.ntt_forward(plan, d[i])
+            torch.cuda.synchronize()
+            assert np.array_equal(host(d), want), f"{name}: forward per polynomial"
+        finally:
+            plan.destroy()
+
+
 def test_config3_full_polymul():
     """N=2^17, L=60 (seed 3), 4 polys: forward x4, products p0*p2 and p1*p3, inverse x2, OT on."""
     N, L, P = 1 << 17, 60, 4
