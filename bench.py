@@ -251,26 +251,32 @@ def main() -> int:
         torch.cuda.synchronize()
         per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
 
-        # per-kernel durations: the same steps with an event between consecutive kernels
+        # per-kernel durations: each kernel launched back to back over K distinct rotating copies,
+        # with events only around each run of K launches (an event between two kernels drains the
+        # queue, and the drain would be charged to the kernel).  Every copy still goes through the
+        # forward passes and then the inverse passes in order, so it ends as it started.
         if fused:
             names = ["fwd_fused", "inv_fused"]
         else:
             names = (["fwd_col", "fwd_row"] if npass == 2 else ["fwd_row"]) + \
                     (["inv_row", "inv_col"] if npass == 2 else ["inv_row"])
-        K = args.steps
-        kev = [[torch.cuda.Event(enable_timing=True) for _ in range(2 * npass + 1)] for _ in range(K)]
-        for i in range(K):
-            b = bufs[i % R]
-            e = kev[i]
-            e[0].record()
+        K = min(R, args.steps)
+        reps = max(1, args.steps // K)
+        runs = []
+        for _ in range(reps):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * npass + 1)]
+            ev[0].record()
             for p in range(npass):
-                ntt.ntt_forward_pass(plan, b, p)
-                e[1 + p].record()
+                for i in range(K):
+                    ntt.ntt_forward_pass(plan, bufs[i], p)
+                ev[1 + p].record()
             for p in range(npass):
-                ntt.ntt_inverse_pass(plan, b, p)
-                e[1 + npass + p].record()
+                for i in range(K):
+                    ntt.ntt_inverse_pass(plan, bufs[i], p)
+                ev[1 + npass + p].record()
+            runs.append(ev)
         torch.cuda.synchronize()
-        kms = {n: float(np.mean([kev[i][j].elapsed_time(kev[i][j + 1]) for i in range(K)]))
+        kms = {n: float(np.mean([ev[j].elapsed_time(ev[j + 1]) / K for ev in runs]))
                for j, n in enumerate(names)}
 
         # plain path: one call per polynomial

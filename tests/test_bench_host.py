@@ -33,6 +33,11 @@ def test_committed_traffic_covers_its_configuration():
     assert keys
     for k in keys:
         assert b.read_traffic(k, h) > 0
+    # the plans that win the headline measurement on some box carry instruction counts as well
+    for plan in ("table-split-n1=6", "table-split-n1=8", "ot1-split-n1=6"):
+        for kern in ("fwd_col", "fwd_row", "inv_row", "inv_col"):
+            assert b.read_traffic(f"{plan}:{kern}", h) > 0
+            assert b.read_traffic(f"{plan}:{kern}", h, field="valu_insts_per_launch") > 0
 
 
 def test_plan_names():
