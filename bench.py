@@ -207,6 +207,21 @@ def main() -> int:
         log(f"profile run: {args.steps} steps ({mode}) + one {ct_bytes}-byte device copy")
         return 0
 
+    # plan creation (prime checks, roots, twiddle, Shoup and OT tables, upload): host time per
+    # plan, median of 3, after a first untimed creation has loaded the library's kernels
+    plan_ms = {}
+    for mode in ("table-split", "ot-split"):
+        ntt.ntt_plan_create(N, primes, log2_n1=args.log2_n1, **VARIANTS[mode]).destroy()
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            pl = ntt.ntt_plan_create(N, primes, log2_n1=args.log2_n1, **VARIANTS[mode])
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+            pl.destroy()
+        plan_ms[mode] = round(float(np.median(ts)), 2)
+    log("plan creation (ms): " + ", ".join(f"{k}={v}" for k, v in plan_ms.items()))
+
     variants = dict(VARIANTS)
     tuned = None
     if args.variant in ("auto", "tuned") and not args.no_tune:
@@ -363,6 +378,7 @@ def main() -> int:
         "modes_us_per_step": {m: round(results[m]["ms"] * 1e3, 2) for m in results},
         "roundtrip_ok": r["roundtrip_ok"],
         "autotune": tuned,
+        "plan_create_ms": plan_ms,
         "polymul": polymul,
         "uneven_batch": uneven,
         "serving": serving,
