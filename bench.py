@@ -207,8 +207,8 @@ def main() -> int:
         log(f"profile run: {args.steps} steps ({mode}) + one {ct_bytes}-byte device copy")
         return 0
 
-    # plan creation (prime checks, roots, twiddle, Shoup and OT tables, upload): host time per
-    # plan, median of 3, after a first untimed creation has loaded the library's kernels
+    # plan creation (prime checks, roots, twiddle, Shoup and OT tables, allocation and upload;
+    # no kernel launch): host time per plan, median of 3 after one untimed creation
     plan_ms = {}
     for mode in ("table-split", "ot-split"):
         ntt.ntt_plan_create(N, primes, log2_n1=args.log2_n1, **VARIANTS[mode]).destroy()
