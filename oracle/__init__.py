@@ -162,6 +162,16 @@ def schoolbook(a, b, q: int) -> np.ndarray:
     return c
 
 
+def natural_order(x) -> np.ndarray:
+    """Slots of the last axis in natural order: slot k of the result is slot brv(k) of x
+    (Algorithm 1's output holds A_brv(i) in slot i, so this gives A_k in slot k)."""
+    x = _u64(x)
+    N = x.shape[-1]
+    b = N.bit_length() - 1
+    idx = np.array([py.bitrev(k, b) for k in range(N)], dtype=np.int64)
+    return np.ascontiguousarray(x[..., idx])
+
+
 def roots(primes, N: int) -> list[int]:
     """The root convention for every prime: smallest primitive 2N-th root of unity."""
     return [find_psi(int(q), N) for q in primes]

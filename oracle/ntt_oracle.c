@@ -61,33 +61,42 @@ static int build_brv_table(uint64_t* table, uint32_t N, uint64_t q, uint64_t roo
     return 0;
 }
 
+/* Algorithm 1 taken stage by stage over blocks: a stage cuts the vector into blocks of
+ * `span` slots (span = N, N/2, ..., 2).  Block b, starting at slot b*span, pairs each slot
+ * of its first half with the slot span/2 above it and uses the twiddle Psi[N/span + b]:
+ * the Cooley-Tukey butterfly of Algorithm 2, (x, y) -> (x + w y, x - w y), fully reduced. */
 static void forward_one(uint64_t* a, uint32_t N, uint64_t q, const uint64_t* Psi) {
-    uint32_t t = N / 2;
-    for (uint32_t m = 1; m < N; m *= 2) {
-        for (uint32_t j = 0; j < m; ++j) {
-            uint64_t w = Psi[m + j];
-            for (uint32_t k = 2 * j * t; k < 2 * j * t + t; ++k) {
-                uint64_t v = mulmod(a[k + t], w, q);
-                a[k + t] = submod(a[k], v, q);
-                a[k] = addmod(a[k], v, q);
+    for (uint32_t span = N; span >= 2; span /= 2) {
+        const uint32_t half = span / 2, blocks = N / span;
+        for (uint32_t b = 0; b < blocks; ++b) {
+            const uint64_t w = Psi[blocks + b];
+            uint64_t* lo = a + (uint64_t)b * span;
+            uint64_t* hi = lo + half;
+            for (uint32_t k = 0; k < half; ++k) {
+                const uint64_t v = mulmod(hi[k], w, q);
+                hi[k] = submod(lo[k], v, q);
+                lo[k] = addmod(lo[k], v, q);
             }
         }
-        t /= 2;
     }
 }
 
+/* The Gentleman-Sande inverse: the same blocks visited from span 2 up to span N, each
+ * butterfly (x, y) -> (x + y, (x - y) w) with w = Psi_inv[N/span + b], then every slot times
+ * N^{-1}. */
 static void inverse_one(uint64_t* a, uint32_t N, uint64_t q, const uint64_t* Pinv, uint64_t n_inv) {
-    uint32_t t = 1;
-    for (uint32_t m = N / 2; m >= 1; m /= 2) {
-        for (uint32_t j = 0; j < m; ++j) {
-            uint64_t w = Pinv[m + j];
-            for (uint32_t k = 2 * j * t; k < 2 * j * t + t; ++k) {
-                uint64_t u = a[k], v = a[k + t];
-                a[k] = addmod(u, v, q);
-                a[k + t] = mulmod(submod(u, v, q), w, q);
+    for (uint32_t span = 2; span <= N; span *= 2) {
+        const uint32_t half = span / 2, blocks = N / span;
+        for (uint32_t b = 0; b < blocks; ++b) {
+            const uint64_t w = Pinv[blocks + b];
+            uint64_t* lo = a + (uint64_t)b * span;
+            uint64_t* hi = lo + half;
+            for (uint32_t k = 0; k < half; ++k) {
+                const uint64_t x = lo[k], y = hi[k];
+                lo[k] = addmod(x, y, q);
+                hi[k] = mulmod(submod(x, y, q), w, q);
             }
         }
-        t *= 2;
     }
     for (uint32_t i = 0; i < N; ++i) a[i] = mulmod(a[i], n_inv, q);
 }

@@ -14,7 +14,9 @@ What each function follows:
   A_k = sum_n a_n psi_{2N}^{n(2k+1)}, with the output written in bit-reversed order
   as Algorithm 1 leaves it (output slot i holds A_{brv(i)}).
 * ``forward_radix2`` -- Algorithm 1 (Cooley-Tukey) with the butterfly of
-  Algorithm 2, every value fully reduced mod q.
+  Algorithm 2, every value fully reduced mod q, taken stage by stage over blocks.
+* ``forward_natural_definition`` -- the same transform with A_k in slot k (the natural
+  order of Section III-C), for the library's natural-order option.
 * ``inverse_definition`` / ``inverse_gs`` -- the inverse with the Psi^{-1} twist
   and the 1/N scale merged in (Section III-A says the merge is possible; the
   paper prints no inverse algorithm, so the Gentleman-Sande form used here is
@@ -148,27 +150,43 @@ def forward_at(a: list[int], q: int, psi: int, i: int) -> int:
 
 
 def forward_radix2(a: list[int], q: int, psi: int) -> list[int]:
-    """Algorithm 1: radix-2 Cooley-Tukey, in place, bit-reversed output.
-
-    Stage m = 1, 2, ..., N/2 with half-span t = N/(2m); block j < m pairs
-    (k, k+t) for k in [2jt, 2jt+t) and applies the butterfly of Algorithm 2 with
-    twiddle Psi[m+j], here with every result fully reduced mod q.
+    """Algorithm 1 (radix-2 Cooley-Tukey), bit-reversed output, taken stage by stage over
+    blocks: a stage cuts the vector into blocks of ``span`` slots (span = N, N/2, ..., 2);
+    block b pairs each slot of its first half with the slot span/2 above it and applies the
+    butterfly of Algorithm 2, (x, y) -> (x + w y, x - w y), with w = Psi[N/span + b], every
+    result fully reduced mod q.
     """
     a = [int(x) % q for x in a]
     N = len(a)
     Psi = psi_table(q, psi, N)
-    t = N // 2
-    m = 1
-    while m < N:
-        for j in range(m):
-            w = Psi[m + j]
-            for k in range(2 * j * t, 2 * j * t + t):
-                v = a[k + t] * w % q
-                a[k + t] = (a[k] - v) % q
+    span = N
+    while span >= 2:
+        half, blocks = span // 2, N // span
+        for b in range(blocks):
+            w = Psi[blocks + b]
+            lo = b * span
+            for k in range(lo, lo + half):
+                v = a[k + half] * w % q
+                a[k + half] = (a[k] - v) % q
                 a[k] = (a[k] + v) % q
-        m *= 2
-        t //= 2
+        span //= 2
     return a
+
+
+def forward_natural_definition(a: list[int], q: int, psi: int) -> list[int]:
+    """O(N^2) merged-twist NTT in natural order (Section III-C's other output order):
+    out[k] = A_k = sum_n a_n psi^{n(2k+1)}, the polynomial at the k-th root psi^{2k+1}."""
+    N = len(a)
+    out = []
+    for k in range(N):
+        w = pow(psi, 2 * k + 1, q)
+        acc = 0
+        wn = 1
+        for n in range(N):
+            acc = (acc + a[n] * wn) % q
+            wn = wn * w % q
+        out.append(acc)
+    return out
 
 
 # ------------------------------------------------------------------ inverse
@@ -191,25 +209,25 @@ def inverse_definition(A: list[int], q: int, psi: int) -> list[int]:
 def inverse_gs(A: list[int], q: int, psi: int) -> list[int]:
     """Gentleman-Sande inverse of Algorithm 1: bit-reversed input, natural-order output.
 
-    Stages run in the reverse order of Algorithm 1 (m = N/2, ..., 1; t = 1, 2, ...,
-    N/2).  Each butterfly maps (U, V) to (U + V, (U - V) * Psi_inv[m+j]) with
+    The blocks of ``forward_radix2`` visited in the opposite order (span = 2, 4, ..., N);
+    block b maps each pair (x, y) to (x + y, (x - y) * Psi_inv[N/span + b]) with
     Psi_inv[i] = psi^{-brv(i)}; every output is finally multiplied by N^{-1}.
     """
     a = [int(x) % q for x in A]
     N = len(a)
     psi_inv = pow(psi, q - 2, q)
     Pinv = psi_table(q, psi_inv, N)
-    t = 1
-    m = N // 2
-    while m >= 1:
-        for j in range(m):
-            w = Pinv[m + j]
-            for k in range(2 * j * t, 2 * j * t + t):
-                u, v = a[k], a[k + t]
-                a[k] = (u + v) % q
-                a[k + t] = (u - v) * w % q
-        t *= 2
-        m //= 2
+    span = 2
+    while span <= N:
+        half, blocks = span // 2, N // span
+        for b in range(blocks):
+            w = Pinv[blocks + b]
+            lo = b * span
+            for k in range(lo, lo + half):
+                x, y = a[k], a[k + half]
+                a[k] = (x + y) % q
+                a[k + half] = (x - y) * w % q
+        span *= 2
     n_inv = pow(N, q - 2, q)
     return [x * n_inv % q for x in a]
 

@@ -300,20 +300,21 @@ def _mutant_forward(kind):
             Psi = [pow(psi, i, q) for i in range(N)]
         if kind == "omega_not_psi":
             Psi = [pow(psi * psi % q, O.bitrev(i, b), q) for i in range(N)]
-        t, m = N // 2, 1
-        while m < N:
-            for j in range(m):
-                w = Psi[j if kind == "index_j" else m + j]
-                for k in range(2 * j * t, 2 * j * t + t):
-                    v = a[k + t] * w % q
+        span = N
+        while span >= 2:
+            half, blocks = span // 2, N // span
+            for j in range(blocks):
+                w = Psi[j if kind == "index_j" else blocks + j]
+                for k in range(j * span, j * span + half):
+                    v = a[k + half] * w % q
                     if kind == "sign":
-                        a[k + t], a[k] = (a[k] + v) % q, (a[k] - v) % q
+                        a[k + half], a[k] = (a[k] + v) % q, (a[k] - v) % q
                     elif kind == "operand":
                         v = a[k] * w % q
-                        a[k + t], a[k] = (a[k + t] - v) % q, (a[k + t] + v) % q
+                        a[k + half], a[k] = (a[k + half] - v) % q, (a[k + half] + v) % q
                     else:
-                        a[k + t], a[k] = (a[k] - v) % q, (a[k] + v) % q
-            m, t = m * 2, t // 2
+                        a[k + half], a[k] = (a[k] - v) % q, (a[k] + v) % q
+            span //= 2
         return a
     return fwd
 
@@ -342,3 +343,50 @@ def test_pins_accept_the_oracle():
 @pytest.mark.parametrize("kind", ["no_bitrev", "omega_not_psi", "index_j", "sign", "operand"])
 def test_pins_reject_planted_mistakes(kind):
     assert not _pins_hold(_mutant_forward(kind))
+
+
+# ----------------------------------------------------------------- natural order (Section III-C)
+
+def _natural_pins_hold(fwd_nat):
+    """Pins of a natural-order forward transform: e_1 goes to the N roots psi^(2k+1) of
+    X^N + 1 in increasing exponent order (each a root, all distinct), and the transform turns
+    the negacyclic convolution (numpy's integer convolution, folded) into the slot-wise
+    product."""
+    q, N = 7681, 32
+    psi = O.find_psi(q, N)
+    e1 = [0, 1] + [0] * (N - 2)
+    xs = fwd_nat(e1, q, psi)
+    if len(set(xs)) != N or any(pow(x, N, q) != q - 1 for x in xs):
+        return False
+    if any(xs[k + 1] != xs[k] * psi * psi % q for k in range(N - 1)) or xs[0] != psi:
+        return False
+    rnd = random.Random(3)
+    a = [rnd.randrange(q) for _ in range(N)]
+    b = [rnd.randrange(q) for _ in range(N)]
+    prod = [x * y % q for x, y in zip(fwd_nat(a, q, psi), fwd_nat(b, q, psi))]
+    return prod == fwd_nat(_numpy_negacyclic(a, b, q), q, psi)
+
+
+def test_natural_definition_pins():
+    assert _natural_pins_hold(O.forward_natural_definition)
+
+
+def test_natural_pins_reject_planted_mistakes():
+    # the twist dropped (psi^(2k) instead of psi^(2k+1)): a cyclic transform
+    def untwisted(a, q, psi):
+        N = len(a)
+        return [sum(a[n] * pow(psi, 2 * k * n, q) for n in range(N)) % q for k in range(N)]
+    # Algorithm 1's bit-reversed order passed off as natural
+    assert not _natural_pins_hold(untwisted)
+    assert not _natural_pins_hold(O.forward_definition)
+
+
+def test_natural_order_of_the_c_oracle():
+    """natural_order() of the C oracle's (bit-reversed) forward output equals the natural
+    definition, computed independently in Python."""
+    q_list = synth.gen_primes(77, 64, 60, 2)
+    psis = oracle.roots(q_list, 64)
+    data = synth.residue_batch(77, q_list, 64, 1)
+    nat = oracle.natural_order(oracle.forward(data, q_list, psis))
+    for l, q in enumerate(q_list):
+        assert nat[0, l].tolist() == O.forward_natural_definition(data[0, l].tolist(), q, psis[l])
