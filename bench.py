@@ -19,7 +19,6 @@ CPU oracle timed on this host.  Everything else goes to stderr.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -44,13 +43,9 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2012_01968_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp", ".cpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
-    return h.hexdigest()[:16]
+    """Hash of the kernels' device-code sources (the tuner's cache key uses the same one)."""
+    from paper_2012_01968_amd import autotune
+    return autotune.source_hash()
 
 
 def ramp(step, ms: float) -> None:
@@ -153,6 +148,7 @@ def main() -> int:
                     help="arrival rate of a second, 5-second stream above the per-request path's capacity (0 skips)")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch section")
     ap.add_argument("--no-polymul", action="store_true", help="skip the large-parameter product section")
+    ap.add_argument("--no-ablation", action="store_true", help="skip the Table II ablation-ladder section")
     ap.add_argument("--profile-polymul", action="store_true",
                     help="counter-collection driver for the product workload: --steps products with one "
                          "twiddle mode (--variant, --log2-n1), then one plain device copy of an operand")
@@ -350,11 +346,18 @@ def main() -> int:
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(host, primes, N, r["plan"], bufs, dev0, n_limb_ntts)
+    # the same kernel against what a plain device copy reaches on this GPU (the copies overwrite
+    # the rotating buffers, which are not used after this)
+    copy_gbs = copy_bandwidth(torch, bufs)
+    roofline["copy_gbs"] = round(copy_gbs, 1)
+    roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    log(f"device copy: {copy_gbs:.0f} GB/s; dominant kernel at {achieved / copy_gbs:.3f} of it")
     for m in results:
         results[m]["plan"].destroy()
     del bufs
     torch.cuda.empty_cache()
     polymul = None if args.no_polymul else polymul_bench(args)
+    ablation = None if args.no_ablation else ablation_bench(args)
     uneven = None if args.no_uneven else uneven_batch_bench(args)
     serving = serve_bench(args) if args.serve_seconds > 0 else None
 
@@ -380,6 +383,7 @@ def main() -> int:
         "autotune": tuned,
         "plan_create_ms": plan_ms,
         "polymul": polymul,
+        "ablation": ablation,
         "uneven_batch": uneven,
         "serving": serving,
         "source_hash": src_hash,
@@ -491,10 +495,7 @@ def uneven_batch_bench(args):
 
     cfg = UNEVEN
     Lmax = cfg["L"][1]
-    chain = synth.gen_primes(cfg["seed"], 1 << max(cfg["logNs"]), cfg["bits"], Lmax)
-    rng = np.random.default_rng(cfg["seed"])
-    logNs = rng.choice(cfg["logNs"], size=cfg["polys"], p=cfg["weights"])
-    Ls = rng.integers(cfg["L"][0], cfg["L"][1] + 1, size=cfg["polys"])
+    chain, logNs, Ls = uneven_jobs(cfg)
     plans, plan_names = {}, {}
     for k in cfg["logNs"]:
         k = int(k)
@@ -545,10 +546,124 @@ def uneven_batch_bench(args):
         log(f"[uneven {name}] {ms:.3f} ms/step  {limb_ntts / ms / 1e3:.3f} M limb-NTTs/s")
     ok = all(torch.equal(b, src[k][:L]) for b, k, L in zip(bufs, logNs.tolist(), Ls.tolist()))
     out["roundtrip_ok"] = bool(ok)
+    out["matches_oracle"] = uneven_forward_matches_oracle(plans, src, chain, logNs, Ls, Lmax)
+    log(f"[uneven] forward of all {cfg['polys']} polys (grouped and graph runs) "
+        f"{'matches' if out['matches_oracle'] else 'DIFFERS FROM'} the oracle")
     out["graph_vs_plain"] = round(out["plain"]["ms_per_step"] / out["graph"]["ms_per_step"], 3)
     batch.destroy()
     for p in plans.values():
         p.destroy()
+    return out
+
+
+def uneven_jobs(cfg=None):
+    """The uneven workload: the prime chain, each polynomial's log2 N and limb count."""
+    import synth
+    cfg = cfg or UNEVEN
+    chain = synth.gen_primes(cfg["seed"], 1 << max(cfg["logNs"]), cfg["bits"], cfg["L"][1])
+    rng = np.random.default_rng(cfg["seed"])
+    logNs = rng.choice(cfg["logNs"], size=cfg["polys"], p=cfg["weights"])
+    Ls = rng.integers(cfg["L"][0], cfg["L"][1] + 1, size=cfg["polys"])
+    return chain, logNs, Ls
+
+
+def uneven_forward_matches_oracle(plans, src, chain, logNs, Ls, Lmax) -> bool:
+    """Forward NTT of every polynomial of the uneven batch (one batch of forward jobs, run
+    grouped and replayed from its graph) against the oracle.  Each polynomial is the first L
+    limbs of its size's source polynomial, so the expected output is the first L limbs of the
+    oracle's forward transform of that source."""
+    import torch
+    import oracle
+    import paper_2012_01968_amd as ntt
+
+    want = {k: oracle.forward(src[k].cpu().numpy().view(np.uint64), chain, oracle.roots(chain, 1 << k),
+                              max(1, min(16, os.cpu_count() or 1))) for k in plans}
+    ok = True
+    for mode in (ntt.BATCH_GROUPED, ntt.BATCH_GRAPH):
+        bufs, jobs = [], []
+        for k, L in zip(logNs.tolist(), Ls.tolist()):
+            b = src[k][:L].clone()
+            bufs.append(b)
+            jobs.append((plans[k], b, 1, L if L < Lmax else 0, ntt.OP_FORWARD))
+        batch = ntt.ntt_batch_create(jobs)
+        ntt.ntt_batch_run(batch, mode)
+        torch.cuda.synchronize()
+        for b, k, L in zip(bufs, logNs.tolist(), Ls.tolist()):
+            ok &= bool(np.array_equal(b.cpu().numpy().view(np.uint64), want[k][:L]))
+        batch.destroy()
+        del bufs
+    return ok
+
+
+ABLATION = dict(logNs=(14, 15, 16, 17), L=21, bits=60, seed=6)
+# Table II (Titan V, microseconds for the 21-limb forward NTT), context only
+PAPER_TABLE2_US = {14: {"radix2": 166, "smem": 48.6, "smem_ot": 44.1}, 15: {"radix2": 340, "smem": 92.0, "smem_ot": 84.2},
+                   16: {"radix2": 693, "smem": 171.8, "smem_ot": 156.3},
+                   17: {"radix2": 1427, "smem": 329.0, "smem_ot": 304.2}}
+
+
+def ablation_bench(args):
+    """The paper's ablation ladder (Table II) on this GPU: forward NTT of one polynomial of 21
+    limbs (60-bit primes, seed 6) at N = 2^14 .. 2^17 by the radix-2 path (one launch per
+    stage), the register-only path at radix 4 .. 32, and the two-pass path with table
+    twiddles and with OT on the last two stages (base 2^10).  Inputs rotate through copies
+    larger than the Infinity Cache; each plan's first forward is checked against the oracle."""
+    import torch
+    import oracle
+    import synth
+    import paper_2012_01968_amd as ntt
+
+    cfg = ABLATION
+    L = cfg["L"]
+    variants = {"radix2": dict(kernel_path=ntt.PATH_RADIX2)}
+    for k in (2, 3, 4, 5):
+        variants[f"register_radix{1 << k}"] = dict(kernel_path=ntt.PATH_REGISTER, log2_radix=k)
+    variants["two_pass_table"] = dict(kernel_path=ntt.PATH_SPLIT)
+    variants["two_pass_ot"] = dict(kernel_path=ntt.PATH_SPLIT, twiddle_mode=ntt.TWIDDLE_OT, ot_stages=2,
+                                   ot_log2_base=10)
+    out = {"workload": f"forward NTT of 1 poly x {L} limbs (60-bit primes, seed {cfg['seed']}), N = 2^14..2^17; "
+                       "Table II's ladder", "paper_titan_v_us": PAPER_TABLE2_US}
+    steps = max(5, min(args.steps, 40))
+    for logN in cfg["logNs"]:
+        N = 1 << logN
+        primes = synth.gen_primes(cfg["seed"], N, cfg["bits"], L)
+        host = synth.residue_batch(cfg["seed"], primes, N, 1)
+        want = oracle.forward(host, primes, oracle.roots(primes, N), max(1, min(16, os.cpu_count() or 1)))
+        x = torch.from_numpy(host.view(np.int64)).to("cuda")
+        R = max(2, int(np.ceil(512 * 2**20 / (x.numel() * 8))))
+        bufs = x.unsqueeze(0).repeat(R, 1, 1, 1)
+        row = {}
+        ok = True
+        for name, opts in variants.items():
+            plan = ntt.ntt_plan_create(N, primes, **opts)
+            d = x.clone()
+            ntt.ntt_forward(plan, d)
+            torch.cuda.synchronize()
+            ok &= bool(np.array_equal(d.cpu().numpy().view(np.uint64), want))
+            ramp(lambda i: ntt.ntt_forward(plan, bufs[i % R]), args.ramp_ms)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for i in range(steps):
+                ntt.ntt_forward(plan, bufs[i % R])
+            e1.record()
+            torch.cuda.synchronize()
+            row[name + "_us"] = round(e0.elapsed_time(e1) * 1e3 / steps, 2)
+            plan.destroy()
+        reg = {k: row[f"register_radix{1 << k}_us"] for k in (2, 3, 4, 5)}
+        best_k = min(reg, key=reg.get)
+        row["best_register_radix"] = 1 << best_k
+        row["speedup_two_pass_ot_vs_radix2"] = round(row["radix2_us"] / row["two_pass_ot_us"], 3)
+        row["speedup_two_pass_table_vs_radix2"] = round(row["radix2_us"] / row["two_pass_table_us"], 3)
+        row["speedup_best_register_vs_radix2"] = round(row["radix2_us"] / reg[best_k], 3)
+        row["ot_gain"] = round(row["two_pass_table_us"] / row["two_pass_ot_us"] - 1, 4)
+        row["limb_ntts_per_s_two_pass_best"] = round(
+            L / (min(row["two_pass_table_us"], row["two_pass_ot_us"]) * 1e-6), 1)
+        row["matches_oracle"] = ok
+        out[str(logN)] = row
+        log(f"[ablation 2^{logN} x {L}] " + ", ".join(f"{k}={v}" for k, v in row.items()))
+        del bufs, x
+        torch.cuda.empty_cache()
     return out
 
 
@@ -631,35 +746,89 @@ def serve_bench(args):
     return out
 
 
-def cpu_baseline(host, primes, N, plan, bufs, dev0, n_limb_ntts):
-    """The CPU oracle (plain C, __int128 %) on this host: forward + inverse of the same
-    ciphertext, repeated until about 3 s of wall time; also checks the GPU forward output
-    of that ciphertext against the oracle's."""
+def host_cpu_facts() -> dict:
+    """What the CPU baseline ran on: logical CPUs, CPUs this process may use, and the model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = os.cpu_count() or 1
+    return {"nproc": os.cpu_count(), "affinity_cpus": affinity, "cpu_model": model}
+
+
+def cpu_baseline(host, primes, N, plan, bufs, dev0, n_limb_ntts, seconds: float = 6.0):
+    """The CPU oracle (plain C, __int128 %) on this host, in two legs: one thread, and one
+    thread per CPU this process may use (at most 16, the host's CPU share per GPU).  Each leg
+    repeats forward + inverse of the same ciphertext until about `seconds` of wall time.
+    Also checks the GPU forward output of that ciphertext against the oracle's."""
     import torch
     import oracle
     import paper_2012_01968_amd as ntt
 
-    threads = max(1, min(16, os.cpu_count() or 1))
+    facts = host_cpu_facts()
     psis = oracle.roots(primes, N)
-    reps = 0
-    t0 = time.perf_counter()
-    f = None
-    while True:
-        f = oracle.forward(host, primes, psis, threads)
-        back = oracle.inverse(f, primes, psis, threads)
-        reps += 1
-        if time.perf_counter() - t0 > 3.0:
-            break
-    wall = time.perf_counter() - t0
+
+    def leg(threads):
+        reps = 0
+        t0 = time.perf_counter()
+        while True:
+            f = oracle.forward(host, primes, psis, threads)
+            back = oracle.inverse(f, primes, psis, threads)
+            reps += 1
+            if time.perf_counter() - t0 > seconds:
+                break
+        wall = time.perf_counter() - t0
+        return reps, wall, f, back
+
+    r1, w1, _, _ = leg(1)
+    threads = max(1, min(16, facts["affinity_cpus"]))
+    reps, wall, f, back = leg(threads)
     d = dev0.clone()
     ntt.ntt_forward(plan, d)
     torch.cuda.synchronize()
     parity = bool(np.array_equal(d.cpu().numpy().view(np.uint64), f) and np.array_equal(back, host))
-    log(f"cpu oracle: {reps} step(s) in {wall:.2f} s on {threads} threads; GPU forward parity={parity}")
+    log(f"cpu oracle: 1 thread {r1} step(s) in {w1:.2f} s; {threads} threads {reps} step(s) in {wall:.2f} s "
+        f"({facts['cpu_model']}, nproc {facts['nproc']}, affinity {facts['affinity_cpus']}); "
+        f"GPU forward parity={parity}")
     return {"value": round(n_limb_ntts * reps / wall, 1), "unit": "limb-NTTs/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{reps} full step(s): forward+inverse of the 2x45x2^16 ciphertext (radix-2, __int128 %)",
+            "sample": f"{reps} full step(s) on {threads} threads: forward+inverse of the 2x45x2^16 ciphertext "
+                      f"(radix-2, __int128 %), threads over limb-vectors",
+            "one_core": {"value": round(n_limb_ntts * r1 / w1, 1), "cores": 1,
+                         "sample": f"{r1} full step(s) on 1 thread"},
+            **facts,
             "gpu_forward_matches": parity}
+
+
+def copy_bandwidth(torch, bufs) -> float:
+    """Device-to-device copy rate (GB/s, bytes read + written) over the rotating copies: copy
+    i reads ciphertext i of the first half and writes ciphertext i of the second half, back to
+    back between two events.  Every read hits a buffer last touched more than the Infinity
+    Cache's size ago, so the rate is HBM's."""
+    R = bufs.shape[0]
+    H = R // 2
+    nbytes = bufs[0].numel() * 8
+    bufs[H].copy_(bufs[0])
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for i in range(H):
+            bufs[H + i].copy_(bufs[i])
+        e1.record()
+        torch.cuda.synchronize()
+        gbs = 2 * nbytes * H / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        best = gbs if best is None else max(best, gbs)
+    return best
 
 
 if __name__ == "__main__":

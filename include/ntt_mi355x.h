@@ -32,8 +32,9 @@
  *               surface at the caller's next synchronisation with the stream.
  *               No C++ exception crosses this interface.
  * Threads       A plan is immutable after creation and may be used from any host
- *               thread and stream at once, except that ntt_polymul_negacyclic uses
- *               plan-owned scratch and serialises on an internal lock.
+ *               thread and stream at once.  ntt_polymul_negacyclic keeps one scratch
+ *               buffer per stream, so products on different streams never wait for each
+ *               other.
  */
 #ifndef NTT_MI355X_H
 #define NTT_MI355X_H
@@ -71,8 +72,34 @@ typedef struct {
     int32_t log2_n1;        /* size of the first (column) pass, N = N1 * N2; 0 = auto;  */
                             /* -1 forces the single-pass kernel where N allows it       */
     int32_t kernel_path;    /* NTT_PATH_*: how the two passes are launched               */
-    int32_t reserved[3];    /* must be zero                                             */
+    int32_t use_autotune;   /* 1: fill the fields above that are zero from the tuner's   */
+                            /* measured choice for this shape (see below); 0: do not    */
+    int32_t tune_polys;     /* polynomials per call the plan is tuned for; 0 = 1         */
+    int32_t order;          /* NTT_ORDER_*: slot order of the NTT domain (see below)     */
+    int32_t log2_radix;     /* NTT_PATH_REGISTER: stages per launch, 2..5; 0 = 4         */
+    int32_t reserved[2];    /* must be zero                                             */
 } ntt_plan_opts;
+
+/* Slot order of the NTT domain (Section III-C).  BITREV (the default) is Algorithm 1's own
+ * order: forward output slot i holds A_{brv(i)}, and the inverse takes that order.  NATURAL
+ * puts A_i in slot i: the forward transform ends with an in-place bit-reversal permutation
+ * of every vector and the inverse begins with one (one more read and write of the data per
+ * transform, the cost for which the paper keeps HE in bit-reversed order).  The order
+ * applies to ntt_forward / ntt_inverse (and their passes) and to the NTT-domain keys of
+ * batch jobs; ntt_pointwise_mul works in either order and ntt_polymul_negacyclic does not
+ * depend on it. */
+enum { NTT_ORDER_BITREV = 0, NTT_ORDER_NATURAL = 1 };
+
+/* Tuned plans (Section VI-C's choice of kernel sizes, Section VII's OT depth and base, made
+ * by measurement).  The Python tuner (paper_2012_01968_amd/autotune.py) writes its choices to
+ * a text file, one line per shape:
+ *   <arch>:<CUs>CU <kernel source hash> <N> <L> <P> <prime bits> <log2_n1> <twiddle_mode>
+ *   <ot_stages> <ot_log2_base> <kernel_path>
+ * With use_autotune = 1, ntt_plan_create reads $NTT_TUNE_FILE, else tune_cache.txt in the
+ * library's directory, and takes the line for the current device, the kernels this library
+ * was built from, N and the primes' width: the one with L and P = tune_polys if present, else
+ * the one whose L*P is nearest.  No line (or no file) leaves the defaults; that is not an
+ * error.  ntt_plan_tuned reports which happened. */
 
 /* Kernel paths for two-pass plans.  SPLIT launches the column pass and the row pass as
  * two kernels.  FUSED runs both in one persistent launch whose workgroups drain
@@ -82,7 +109,17 @@ typedef struct {
  * AUTO takes SPLIT (measured faster on MI355X).  Launches of one FUSED plan share a small counter
  * block, so the library orders them across streams (a launch on another stream waits for
  * the previous one). */
-enum { NTT_PATH_AUTO = 0, NTT_PATH_SPLIT = 1, NTT_PATH_FUSED = 2 };
+enum { NTT_PATH_AUTO = 0, NTT_PATH_SPLIT = 1, NTT_PATH_FUSED = 2, NTT_PATH_RADIX2 = 3, NTT_PATH_REGISTER = 4 };
+
+/* The two paths of the paper's ablation ladder (Section VI-A, VI-B; Table II), kept for
+ * comparison with the split design: the data goes back to global memory after every group
+ * of stages, and twiddles come from the table (no OT, no column/row split).
+ *   RADIX2    one launch per stage of Algorithm 1, one butterfly per lane (log2 N launches);
+ *   REGISTER  one launch per log2_radix consecutive stages, each lane holding the 2^log2_radix
+ *             elements of one group of butterflies in registers (ceil(log2 N / log2_radix)
+ *             launches; the last group may be shorter).
+ * Both give the same results as every other path; ntt_forward_pass / ntt_inverse_pass run one
+ * launch each (ntt_plan_num_passes of them). */
 
 /* Create a plan for length-N transforms over L primes (Section III-B; Algorithm 1
  * REQUIRE: each q = 1 mod 2N).  `primes` is a host array of L distinct primes with
@@ -95,15 +132,20 @@ enum { NTT_PATH_AUTO = 0, NTT_PATH_SPLIT = 1, NTT_PATH_FUSED = 2 };
 ntt_status ntt_plan_create(ntt_plan_t* out, uint32_t N, const uint64_t* primes, uint32_t L,
                            const ntt_plan_opts* opts);
 
-/* Release a plan and its device memory.  The caller must make sure no enqueued
- * work still uses it (synchronise the streams first).  NULL is accepted. */
+/* Drop the creator's reference to a plan.  A batch that names the plan holds a reference
+ * of its own, so the plan stays usable by that batch (and only by it: every other call on
+ * the handle returns NTT_ERR_ARG) until the last such batch is reassigned or destroyed.  The
+ * call that drops the last reference frees the plan; the free first waits for all work queued
+ * on the plan's device, so kernels already enqueued with the plan finish before its tables go.
+ * NULL is accepted.  Errors: NTT_ERR_ARG when the plan was already destroyed and is still
+ * held by a batch (a handle whose plan has been freed must not be passed at all). */
 ntt_status ntt_plan_destroy(ntt_plan_t plan);
 
 /* Copy the L roots psi_l in use into the host array psi_out (L entries). */
 ntt_status ntt_plan_get_roots(ntt_plan_t plan, uint64_t* psi_out);
 
-/* N, L, the pass split, twiddle mode, OT stages and kernel path (NTT_PATH_SPLIT or
- * NTT_PATH_FUSED; single-pass plans report SPLIT) chosen by the plan.  Any pointer may be
+/* N, L, the pass split, twiddle mode, OT stages and kernel path (NTT_PATH_SPLIT, FUSED,
+ * RADIX2 or REGISTER; single-pass plans report SPLIT) chosen by the plan.  Any pointer may be
  * NULL. */
 ntt_status ntt_plan_get_info(ntt_plan_t plan, uint32_t* N, uint32_t* L, uint32_t* log2_n1,
                              int32_t* twiddle_mode, int32_t* ot_stages, int32_t* kernel_path);
@@ -111,28 +153,43 @@ ntt_status ntt_plan_get_info(ntt_plan_t plan, uint32_t* N, uint32_t* L, uint32_t
 /* In-place forward NTT of every vector of d_data ([n_polys][L][N] uint64, device).
  * Section III-A merged-twist transform computed as Algorithm 1 (Cooley-Tukey with the
  * butterfly of Algorithm 2 and Shoup's modmul of Algorithm 4) split into an LDS-staged
- * column pass and row pass (Section VI-C).  Output in bit-reversed order. */
+ * column pass and row pass (Section VI-C).  Output in bit-reversed order (natural order
+ * for a NTT_ORDER_NATURAL plan). */
 ntt_status ntt_forward(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, void* stream);
 
 /* One kernel of the forward transform, for callers that schedule or time the passes
  * themselves (Section VI-C's Kernel-1 / Kernel-2).  pass 0 runs the column pass (the
  * first log2 N1 stages), pass 1 the row pass (the remaining stages, final reduction,
- * bit-reversed output).  A single-pass or fused plan has only pass 0.  Running
- * every pass in order equals ntt_forward.  Errors: NTT_ERR_ARG for a pass index at or
- * above ntt_plan_num_passes. */
+ * bit-reversed output).  A single-pass or fused plan has only pass 0.  A natural-order
+ * plan adds the permutation as the last pass.  Running every pass in order equals
+ * ntt_forward.  Errors: NTT_ERR_ARG for a pass index at or above ntt_plan_num_passes. */
 ntt_status ntt_forward_pass(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, uint32_t pass, void* stream);
 
 /* One kernel of the inverse transform: pass 0 runs the row pass (the first
  * Gentleman-Sande stages), pass 1 the column pass (the last stages with the 1/N scale).
- * A single-pass or fused plan has only pass 0.  Running every pass in order equals
+ * A single-pass or fused plan has only pass 0.  A natural-order plan adds the permutation
+ * as the first pass (the others move up by one).  Running every pass in order equals
  * ntt_inverse. */
 ntt_status ntt_inverse_pass(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, uint32_t pass, void* stream);
 
-/* Number of kernels per transform for this plan: 1 (single pass or fused) or 2. */
+/* Number of kernels per transform for this plan: 1 (single pass or fused) or 2, plus one
+ * for the permutation of a natural-order plan; 0 for a NULL or destroyed plan. */
 uint32_t ntt_plan_num_passes(ntt_plan_t plan);
 
-/* In-place inverse: takes bit-reversed NTT-domain vectors and returns natural-order
- * coefficients, with the Psi^{-1} twist and the 1/N scale merged in (Section III-A). */
+/* The plan's NTT-domain slot order (NTT_ORDER_*), -1 for a NULL or destroyed plan. */
+int32_t ntt_plan_order(ntt_plan_t plan);
+
+/* Stages per launch of a RADIX2 (1) or REGISTER plan, 0 for the other paths, -1 for a NULL
+ * or destroyed plan. */
+int32_t ntt_plan_log2_radix(ntt_plan_t plan);
+
+/* 1 when the plan's options came from the tuner's file (use_autotune found a line), 0 when
+ * not, -1 for a NULL or destroyed plan. */
+int32_t ntt_plan_tuned(ntt_plan_t plan);
+
+/* In-place inverse: takes NTT-domain vectors in the plan's order (bit-reversed unless the
+ * plan is NTT_ORDER_NATURAL) and returns natural-order coefficients, with the Psi^{-1}
+ * twist and the 1/N scale merged in (Section III-A). */
 ntt_status ntt_inverse(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, void* stream);
 
 /* Element-wise product in the NTT domain (Section III-A, the Hadamard product):
@@ -143,8 +200,9 @@ ntt_status ntt_pointwise_mul(ntt_plan_t plan, const uint64_t* d_a, const uint64_
 
 /* Negacyclic product in Z_q[X]/(X^N+1) per vector (Section III-A):
  * c = iNTT(NTT(a) * NTT(b)).  Inputs and output are natural-order coefficients;
- * d_a and d_b are left unchanged; d_c may alias d_a but not d_b.  Uses a plan-owned
- * scratch buffer of n_polys*L*N*8 bytes, grown on demand. */
+ * d_a and d_b are left unchanged; d_c may alias d_a but not d_b.  NTT(b) goes to a
+ * plan-owned scratch buffer of n_polys*L*N*8 bytes, one per stream, grown on demand (the
+ * growth waits for the stream's previous product). */
 ntt_status ntt_polymul_negacyclic(ntt_plan_t plan, const uint64_t* d_a, const uint64_t* d_b, uint64_t* d_c,
                                   uint32_t n_polys, void* stream);
 
@@ -165,10 +223,11 @@ ntt_status ntt_polymul_negacyclic(ntt_plan_t plan, const uint64_t* d_a, const ui
  *
  * op is a set of steps run in the order forward, key product, inverse: NTT_OP_MULKEY
  * multiplies every polynomial of the job element-wise by the job's key, a device array
- * [n_limbs][N] already in the NTT domain (the ciphertext-times-plaintext step of
- * Section III-A's polynomial product).  Results
- * are bit-identical across the three modes.  Plans must outlive the batches that use
- * them; the data arrays must stay valid and may not overlap between jobs. */
+ * [n_limbs][N] already in the NTT domain, in the plan's slot order (the
+ * ciphertext-times-plaintext step of Section III-A's polynomial product).  Results
+ * are bit-identical across the three modes.  A batch holds a reference on each plan its
+ * jobs name (see ntt_plan_destroy), so a plan may be destroyed before the batch; the data
+ * arrays must stay valid and may not overlap between jobs. */
 enum { NTT_OP_FORWARD = 1, NTT_OP_INVERSE = 2, NTT_OP_FORWARD_INVERSE = 3, NTT_OP_MULKEY = 4 };
 enum { NTT_BATCH_PLAIN = 0, NTT_BATCH_GROUPED = 1, NTT_BATCH_GRAPH = 2 };
 

@@ -16,17 +16,20 @@ import os
 
 __all__ = [
     "NttError", "Plan", "ntt_plan_create", "ntt_plan_destroy", "ntt_plan_get_roots", "ntt_plan_get_info",
-    "ntt_forward", "ntt_inverse", "ntt_forward_pass", "ntt_inverse_pass", "ntt_plan_num_passes",
+    "ntt_forward", "ntt_inverse", "ntt_forward_pass", "ntt_inverse_pass", "ntt_plan_num_passes", "ntt_plan_tuned",
+    "ntt_plan_order", "ORDER_BITREV", "ORDER_NATURAL",
     "ntt_pointwise_mul", "ntt_polymul_negacyclic", "ntt_status_string",
     "Batch", "ntt_batch_create", "ntt_batch_run", "ntt_batch_destroy", "ntt_batch_assign", "OP_FORWARD", "OP_INVERSE",
     "OP_FORWARD_INVERSE", "OP_MULKEY", "BATCH_PLAIN", "BATCH_GROUPED", "BATCH_GRAPH",
     "library_path", "TWIDDLE_AUTO", "TWIDDLE_TABLE", "TWIDDLE_OT", "PATH_AUTO", "PATH_SPLIT", "PATH_FUSED",
+    "PATH_RADIX2", "PATH_REGISTER", "ntt_plan_log2_radix",
 ]
 
 TWIDDLE_AUTO, TWIDDLE_TABLE, TWIDDLE_OT = 0, 1, 2
-PATH_AUTO, PATH_SPLIT, PATH_FUSED = 0, 1, 2
+PATH_AUTO, PATH_SPLIT, PATH_FUSED, PATH_RADIX2, PATH_REGISTER = 0, 1, 2, 3, 4
 OP_FORWARD, OP_INVERSE, OP_FORWARD_INVERSE, OP_MULKEY = 1, 2, 3, 4
 BATCH_PLAIN, BATCH_GROUPED, BATCH_GRAPH = 0, 1, 2
+ORDER_BITREV, ORDER_NATURAL = 0, 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 # NTT_MI355X_LIB selects another build of the library (e.g. a tuning variant).
@@ -67,7 +70,9 @@ _lib = ctypes.CDLL(_LIB_PATH)
 class _Opts(ctypes.Structure):
     _fields_ = [("twiddle_mode", ctypes.c_int32), ("ot_stages", ctypes.c_int32),
                 ("ot_log2_base", ctypes.c_int32), ("log2_n1", ctypes.c_int32),
-                ("kernel_path", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("kernel_path", ctypes.c_int32), ("use_autotune", ctypes.c_int32),
+                ("tune_polys", ctypes.c_int32), ("order", ctypes.c_int32), ("log2_radix", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 _vp = ctypes.c_void_p
@@ -93,6 +98,12 @@ _lib.ntt_forward_pass.argtypes = [_vp, _vp, _u32, _u32, _vp]
 _lib.ntt_inverse_pass.argtypes = [_vp, _vp, _u32, _u32, _vp]
 _lib.ntt_plan_num_passes.argtypes = [_vp]
 _lib.ntt_plan_num_passes.restype = _u32
+_lib.ntt_plan_tuned.argtypes = [_vp]
+_lib.ntt_plan_order.argtypes = [_vp]
+_lib.ntt_plan_order.restype = ctypes.c_int32
+_lib.ntt_plan_log2_radix.argtypes = [_vp]
+_lib.ntt_plan_log2_radix.restype = ctypes.c_int32
+_lib.ntt_plan_tuned.restype = ctypes.c_int32
 _lib.ntt_pointwise_mul.argtypes = [_vp, _vp, _vp, _vp, _u32, _vp]
 _lib.ntt_polymul_negacyclic.argtypes = [_vp, _vp, _vp, _vp, _u32, _vp]
 _lib.ntt_batch_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_Job), _u32]
@@ -145,11 +156,23 @@ class Plan:
             pass
 
 
-def _addr(buf) -> int:
+def _addr(buf, need: int | None = None, what: str = "buffer") -> int:
+    """Device address of `buf` for the C ABI.  A raw integer is passed through as given (the
+    caller vouches for it).  A tensor must live on the GPU, hold 8-byte integers, be
+    contiguous and have at least `need` elements: anything else would reach the kernels as a
+    pointer to memory they cannot address or to too few elements."""
     if buf is None:
-        raise ValueError("buffer is None")
+        raise ValueError(f"{what} is None")
     if isinstance(buf, int):
         return buf
+    if not getattr(buf, "is_cuda", False):
+        raise ValueError(f"{what} must be a tensor in GPU memory")
+    if buf.element_size() != 8 or buf.dtype.is_floating_point or buf.dtype.is_complex:
+        raise ValueError(f"{what} must hold 64-bit integers (int64 or uint64), not {buf.dtype}")
+    if not buf.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if need is not None and buf.numel() < need:
+        raise ValueError(f"{what} holds {buf.numel()} elements; the call needs {need}")
     return int(buf.data_ptr())
 
 
@@ -164,19 +187,32 @@ def _stream(stream) -> int | None:
 
 def _polys(plan: Plan, buf, n_polys) -> int:
     if n_polys is not None:
+        if int(n_polys) < 1:
+            raise ValueError("n_polys must be at least 1")
         return int(n_polys)
+    if isinstance(buf, int):
+        raise ValueError("n_polys is required when a buffer is given as a raw address")
     numel = buf.numel()
     per = plan.N * plan.L
-    if numel % per:
+    if numel == 0 or numel % per:
         raise ValueError(f"buffer of {numel} elements is not a whole number of [L][N] polynomials")
     return numel // per
 
 
+def _batch_addrs(plan: Plan, bufs, names, n_polys):
+    """n_polys and the addresses of same-shaped [n_polys][L][N] operands."""
+    n = _polys(plan, bufs[0], n_polys)
+    need = n * plan.L * plan.N
+    return n, [_addr(b, need, w) for b, w in zip(bufs, names)]
+
+
 def ntt_plan_create(N: int, primes, *, twiddle_mode: int = 0, ot_stages: int = 0, ot_log2_base: int = 0,
-                    log2_n1: int = 0, kernel_path: int = 0) -> Plan:
+                    log2_n1: int = 0, kernel_path: int = 0, use_autotune: int = 0, tune_polys: int = 0,
+                    order: int = 0, log2_radix: int = 0) -> Plan:
     primes = [int(q) for q in primes]
     arr = (ctypes.c_uint64 * len(primes))(*primes)
-    opts = _Opts(twiddle_mode, ot_stages, ot_log2_base, log2_n1, kernel_path)
+    opts = _Opts(twiddle_mode, ot_stages, ot_log2_base, log2_n1, kernel_path, int(use_autotune), int(tune_polys),
+                 int(order), int(log2_radix))
     h = _vp()
     _check(_lib.ntt_plan_create(ctypes.byref(h), N, arr, len(primes), ctypes.byref(opts)), "ntt_plan_create")
     return Plan(h.value, N, len(primes))
@@ -202,35 +238,61 @@ def ntt_plan_get_info(plan: Plan) -> dict:
 
 
 def ntt_forward(plan: Plan, data, n_polys: int | None = None, stream=None) -> None:
-    _check(_lib.ntt_forward(plan.handle, _addr(data), _polys(plan, data, n_polys), _stream(stream)), "ntt_forward")
+    n, (d,) = _batch_addrs(plan, [data], ["data"], n_polys)
+    _check(_lib.ntt_forward(plan.handle, d, n, _stream(stream)), "ntt_forward")
 
 
 def ntt_inverse(plan: Plan, data, n_polys: int | None = None, stream=None) -> None:
-    _check(_lib.ntt_inverse(plan.handle, _addr(data), _polys(plan, data, n_polys), _stream(stream)), "ntt_inverse")
+    n, (d,) = _batch_addrs(plan, [data], ["data"], n_polys)
+    _check(_lib.ntt_inverse(plan.handle, d, n, _stream(stream)), "ntt_inverse")
 
 
 def ntt_forward_pass(plan: Plan, data, pass_index: int, n_polys: int | None = None, stream=None) -> None:
-    _check(_lib.ntt_forward_pass(plan.handle, _addr(data), _polys(plan, data, n_polys), pass_index, _stream(stream)),
-           "ntt_forward_pass")
+    n, (d,) = _batch_addrs(plan, [data], ["data"], n_polys)
+    _check(_lib.ntt_forward_pass(plan.handle, d, n, pass_index, _stream(stream)), "ntt_forward_pass")
 
 
 def ntt_inverse_pass(plan: Plan, data, pass_index: int, n_polys: int | None = None, stream=None) -> None:
-    _check(_lib.ntt_inverse_pass(plan.handle, _addr(data), _polys(plan, data, n_polys), pass_index, _stream(stream)),
-           "ntt_inverse_pass")
+    n, (d,) = _batch_addrs(plan, [data], ["data"], n_polys)
+    _check(_lib.ntt_inverse_pass(plan.handle, d, n, pass_index, _stream(stream)), "ntt_inverse_pass")
 
 
 def ntt_plan_num_passes(plan: Plan) -> int:
     return int(_lib.ntt_plan_num_passes(plan.handle))
 
 
+def ntt_plan_log2_radix(plan: Plan) -> int:
+    """Stages per launch of a PATH_RADIX2 (1) or PATH_REGISTER plan; 0 for the other paths."""
+    r = int(_lib.ntt_plan_log2_radix(plan.handle))
+    if r < 0:
+        raise NttError(-1, "ntt_plan_log2_radix")
+    return r
+
+
+def ntt_plan_order(plan: Plan) -> int:
+    """ORDER_BITREV or ORDER_NATURAL: the slot order of the plan's NTT domain."""
+    r = int(_lib.ntt_plan_order(plan.handle))
+    if r < 0:
+        raise NttError(-1, "ntt_plan_order")
+    return r
+
+
+def ntt_plan_tuned(plan: Plan) -> bool:
+    """Whether the plan's options came from the tuner's file (use_autotune=1 found its shape)."""
+    r = int(_lib.ntt_plan_tuned(plan.handle))
+    if r < 0:
+        raise NttError(-1, "ntt_plan_tuned")
+    return bool(r)
+
+
 def ntt_pointwise_mul(plan: Plan, a, b, c, n_polys: int | None = None, stream=None) -> None:
-    _check(_lib.ntt_pointwise_mul(plan.handle, _addr(a), _addr(b), _addr(c), _polys(plan, a, n_polys),
-                                  _stream(stream)), "ntt_pointwise_mul")
+    n, (pa, pb, pc) = _batch_addrs(plan, [a, b, c], ["a", "b", "c"], n_polys)
+    _check(_lib.ntt_pointwise_mul(plan.handle, pa, pb, pc, n, _stream(stream)), "ntt_pointwise_mul")
 
 
 def ntt_polymul_negacyclic(plan: Plan, a, b, c, n_polys: int | None = None, stream=None) -> None:
-    _check(_lib.ntt_polymul_negacyclic(plan.handle, _addr(a), _addr(b), _addr(c), _polys(plan, a, n_polys),
-                                       _stream(stream)), "ntt_polymul_negacyclic")
+    n, (pa, pb, pc) = _batch_addrs(plan, [a, b, c], ["a", "b", "c"], n_polys)
+    _check(_lib.ntt_polymul_negacyclic(plan.handle, pa, pb, pc, n, _stream(stream)), "ntt_polymul_negacyclic")
 
 
 class Batch:
@@ -261,9 +323,14 @@ def _jobs_array(jobs):
         key = job[5] if len(job) > 5 else None
         limbs = n_limbs or plan.L
         if n_polys is None:
+            if isinstance(data, int):
+                raise ValueError(f"job {i}: n_polys is required when data is a raw address")
             n_polys = data.numel() // (plan.N * limbs)
-        arr[i] = _Job(plan.handle, _addr(data), int(n_polys), int(n_limbs), int(op), 0,
-                      _addr(key) if key is not None else None)
+        if int(n_polys) < 1:
+            raise ValueError(f"job {i}: n_polys must be at least 1")
+        d = _addr(data, int(n_polys) * limbs * plan.N, f"job {i} data")
+        k = _addr(key, limbs * plan.N, f"job {i} key") if key is not None else None
+        arr[i] = _Job(plan.handle, d, int(n_polys), int(n_limbs), int(op), 0, k)
         keep.append((plan, data, key))
     return arr, keep
 

@@ -5,15 +5,16 @@ tuner times forward+inverse round trips of every plan option set that the librar
 supports for that N:
 
 * the split N = N1 x N2 between the column and the row pass (or one pass for N <= 2^13),
-  as in the paper's choice of kernel sizes for its two-kernel NTT (Sec. IV-B, IV-D);
+  as in the paper's choice of kernel sizes for its two-kernel NTT (Section VI-C);
 * stored twiddle tables, or on-the-fly twiddling on the last one or two stages with a
-  digit base of 2^8, 2^10 or 2^12 (Sec. IV-E);
+  digit base of 2^8, 2^10 or 2^12 (Section VII);
 * the two-launch path, or the single persistent launch where that shape exists.
 
 Tile shapes (values per lane, workgroup size) are fixed when the library is built, so
-they are not part of the search.  Every candidate's output is compared bit for bit with
-the first candidate's on the same input (all of them compute the same exact result), and
-a candidate that differs is dropped and reported.
+they are not part of the search.  Every candidate's forward transform, inverse and
+negacyclic product are compared bit for bit with those of the default plan on the same
+inputs (all of them compute the same exact residues), and its inverse must undo its
+forward transform; a candidate that fails any of these is dropped and reported.
 
 Results are cached in a JSON file keyed by the device, a hash of the kernel sources and
 the shape, so a shape is measured once per library build.  The cache is
@@ -21,31 +22,23 @@ the shape, so a shape is measured once per library build.  The cache is
 """
 from __future__ import annotations
 
-import hashlib
 import json
 import math
 import os
 import time
 
 from . import (PATH_FUSED, PATH_SPLIT, TWIDDLE_OT, TWIDDLE_TABLE, NttError, ntt_forward, ntt_inverse,
-               ntt_plan_create, ntt_plan_get_info)
+               ntt_plan_create, ntt_plan_get_info, ntt_polymul_negacyclic)
 
-__all__ = ["candidates", "source_hash", "cache_path", "lookup", "tune", "plan_create_tuned"]
+__all__ = ["candidates", "source_hash", "cache_path", "flat_path", "flat_lines", "lookup", "tune",
+           "plan_create_tuned"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 FUSED_SHAPES = {(6, 7), (7, 7), (7, 8), (8, 8), (8, 9)}
 MALL_BYTES = 256 << 20
 
 
-def source_hash() -> str:
-    """Hash of the kernel and ABI sources the library is built from."""
-    h = hashlib.sha256()
-    csrc = os.path.join(_HERE, "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp", ".cpp", ".h")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
-    return h.hexdigest()[:16]
+from .build import source_hash  # noqa: E402  (one definition, compiled into the library)
 
 
 def cache_path() -> str:
@@ -100,11 +93,40 @@ def _load(path: str) -> dict:
         return {"version": 1, "entries": {}}
 
 
+def flat_path(path: str | None = None) -> str:
+    """The flat text copy of the cache that the C library reads (use_autotune): the JSON
+    cache's path with a .txt suffix."""
+    base = path or cache_path()
+    return (base[:-5] if base.endswith(".json") else base) + ".txt"
+
+
+def flat_lines(cache: dict) -> list[str]:
+    """One line per cached shape, in the format of csrc/tune_file.hpp:
+    <device> <source_hash> <N> <L> <P> <qbits> <log2_n1> <twiddle_mode> <ot_stages> <ot_log2_base> <kernel_path>"""
+    out = []
+    for key, e in sorted(cache["entries"].items()):
+        parts = key.split("|")
+        if len(parts) != 6:
+            continue
+        dev, h, n, l, p, qb = parts
+        o = e["opts"]
+        vals = [dev, h, n.split("=")[1], l.split("=")[1], p.split("=")[1], qb.split("=")[1],
+                o.get("log2_n1", 0), o.get("twiddle_mode", 0), o.get("ot_stages", 0), o.get("ot_log2_base", 0),
+                o.get("kernel_path", 0)]
+        out.append(" ".join(str(v) for v in vals))
+    return out
+
+
 def _store(path: str, cache: dict) -> None:
     tmp = f"{path}.{os.getpid()}.tmp"
     with open(tmp, "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)
     os.replace(tmp, path)
+    flat = flat_path(path)
+    tmp = f"{flat}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        f.write("".join(line + "\n" for line in flat_lines(cache)))
+    os.replace(tmp, flat)
 
 
 def _inputs(torch, N: int, primes, polys: int, rotate_bytes: int):
@@ -144,6 +166,33 @@ def _time(torch, plan, bufs, steps: int, warmup: int, ramp_s: float = 0.01) -> f
     return e0.elapsed_time(e1) * 1e3 / steps
 
 
+def _outputs(torch, plan, x, x2) -> dict:
+    """Forward, inverse and negacyclic product of the tuning inputs under `plan`."""
+    f = x.clone()
+    ntt_forward(plan, f)
+    i = x.clone()
+    ntt_inverse(plan, i)
+    m = torch.empty_like(x)
+    ntt_polymul_negacyclic(plan, x, x2, m)
+    torch.cuda.synchronize()
+    return {"forward": f, "inverse": i, "product": m}
+
+
+def _disagrees(torch, plan, x, x2, ref) -> str:
+    """Name of the first entry point whose result under `plan` differs from the reference
+    plan's, or of a failed round trip; '' when everything agrees."""
+    out = _outputs(torch, plan, x, x2)
+    for name in ("forward", "inverse", "product"):
+        if not torch.equal(out[name], ref[name]):
+            return name
+    back = out["forward"]
+    ntt_inverse(plan, back)
+    torch.cuda.synchronize()
+    if not torch.equal(back, x):
+        return "inverse(forward)"
+    return ""
+
+
 def lookup(N: int, primes, polys: int = 1, path: str | None = None):
     """The cached entry for this shape on this device and kernel build, or None."""
     import torch
@@ -161,7 +210,14 @@ def tune(N: int, primes, polys: int = 1, *, steps: int = 100, warmup: int = 3, r
     if not refresh and key in cache["entries"]:
         return cache["entries"][key]
     x, bufs = _inputs(torch, N, primes, polys, 2 * MALL_BYTES)
-    ref = None
+    x2 = torch.flip(x, dims=[-1]).contiguous()     # a second operand for the product check
+    # reference results from the default plan: every candidate computes the same exact
+    # residues, so one that differs on any entry point is dropped (and reported)
+    ref_plan = ntt_plan_create(N, primes)
+    try:
+        ref = _outputs(torch, ref_plan, x, x2)
+    finally:
+        ref_plan.destroy()
     tried, dropped, refused = [], [], []
     t0 = time.perf_counter()
     for opts in candidates(N):
@@ -171,13 +227,11 @@ def tune(N: int, primes, polys: int = 1, *, steps: int = 100, warmup: int = 3, r
             refused.append({"opts": opts, "error": str(e)})
             continue
         try:
-            y = x.clone()
-            ntt_forward(plan, y)
-            torch.cuda.synchronize()
-            if ref is None:
-                ref = y
-            elif not torch.equal(y, ref):
-                dropped.append(opts)
+            bad = _disagrees(torch, plan, x, x2, ref)
+            if bad:
+                dropped.append({"opts": opts, "differs": bad})
+                if log:
+                    log(f"  N={N} L={len(primes)} P={polys} {opts}: dropped ({bad} differs)")
                 continue
             us = _time(torch, plan, bufs, steps, warmup)
             info = ntt_plan_get_info(plan)

@@ -18,7 +18,7 @@ BUILD = os.environ.get("NTT_BUILD_DIR") or os.path.join(ROOT, "_build", "ntt")
 LIB = os.environ.get("NTT_BUILD_OUT") or os.path.join(HERE, "libntt_mi355x.so")
 SOURCES = ["kernels_fwd_fast.hip", "kernels_inv_fast.hip", "kernels_fwd_wide.hip", "kernels_inv_wide.hip",
            "kernels_mul_fast.hip", "kernels_mul_wide.hip",
-           "fused_fwd.hip", "fused_inv.hip", "kernels.hip", "capi.cpp"]
+           "fused_fwd.hip", "fused_inv.hip", "kernels.hip", "permute.hip", "stages.hip", "capi.cpp"]
 ARCH = os.environ.get("NTT_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -30,9 +30,27 @@ FLAGS = [
 ] + os.environ.get("NTT_EXTRA_FLAGS", "").split()
 
 
+# Host-only sources: they decide which launches happen but hold no device code, so a change
+# there leaves every kernel's measured time (and the counters taken of it) valid.
+HOST_ONLY_SOURCES = ("capi.cpp", "plan_math.hpp", "plan_life.hpp", "tune_file.hpp")
+
+
+def source_hash() -> str:
+    """Hash of the device-code sources the kernels are built from (the .hip and .hpp files
+    other than the host-only ones).  The library is built with it, and the tuner keys its
+    cache by it: a measured choice or counter stays valid while it is unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".hpp")) and name not in HOST_ONLY_SOURCES:
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, f'-DNTT_SOURCE_HASH="{source_hash()}"', "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr[-6000:]}")

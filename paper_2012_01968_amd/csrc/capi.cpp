@@ -2,11 +2,14 @@
 // Every entry point catches everything; no exception crosses the interface.
 #include "ntt_mi355x.h"
 
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -16,7 +19,13 @@
 
 #include "kernels.hpp"
 #include "passes.hpp"
+#include "plan_life.hpp"
 #include "plan_math.hpp"
+#include "tune_file.hpp"
+
+#ifndef NTT_SOURCE_HASH
+#define NTT_SOURCE_HASH "unknown"
+#endif
 
 using nttk::PassArgs;
 using nttk::Tw;
@@ -69,6 +78,8 @@ struct ntt_plan_s {
   int32_t ot_stages = 0;
   uint32_t ot_log2_base = 10;
   int32_t kernel_path = NTT_PATH_SPLIT;   // SPLIT or FUSED after creation
+  int32_t order = NTT_ORDER_BITREV;       // NTT-domain slot order seen by the caller
+  int32_t log2_radix = 0;                 // RADIX2 / REGISTER paths: stages per launch
   uint32_t fused_lag = 4;                 // vectors an XCD queue runs pass 1 ahead of pass 2
   uint32_t fused_grid = 1024;             // persistent workgroups (4 per CU)
   uint32_t* d_ctr = nullptr;              // fused-launch counters: 16 + kMaxFusedVectors words
@@ -77,6 +88,7 @@ struct ntt_plan_s {
   hipStream_t fused_last = nullptr;
   bool fused_pending = false;
   int device = 0;
+  bool tuned = false; // options taken from the tuner's file (use_autotune)
   bool fast = false;  // all primes below 2^60 (wider lazy ranges, estimated quotients)
   std::vector<uint64_t> primes, psis;
 
@@ -92,24 +104,47 @@ struct ntt_plan_s {
   uint64_t* d_mu = nullptr;
   uint32_t* d_bits = nullptr;
 
-  // polymul scratch: one buffer, ordered across streams by an event
-  std::mutex scratch_mu;
-  uint64_t* scratch = nullptr;
-  size_t scratch_bytes = 0;
-  hipEvent_t scratch_ev = nullptr;
-  bool scratch_pending = false;
+  // References: the creator's and one per batch that names the plan (plan_life.hpp).
+  nttl::RefCount rc;
+
+  // Product scratch (NTT(b) of ntt_polymul_negacyclic), one buffer per stream that has run a
+  // product: work on one stream is ordered, so products on different streams never wait for
+  // each other and products on one stream reuse the buffer in order.  `ev` marks the last
+  // product enqueued with the buffer, which must finish before the buffer is replaced.
+  struct StreamScratch {
+    hipStream_t stream = nullptr;
+    std::mutex mu;
+    uint64_t* buf = nullptr;
+    size_t bytes = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+  };
+  std::mutex stream_scratch_mu;   // guards the list; each entry has its own lock
+  std::vector<std::unique_ptr<StreamScratch>> stream_scratch;
+
+  StreamScratch* scratch_for(hipStream_t st) {
+    std::lock_guard<std::mutex> lk(stream_scratch_mu);
+    for (auto& s : stream_scratch)
+      if (s->stream == st) return s.get();
+    stream_scratch.emplace_back(new StreamScratch());
+    stream_scratch.back()->stream = st;
+    return stream_scratch.back().get();
+  }
 
   ~ntt_plan_s() {
-    if (scratch_ev) {
-      (void)hipEventSynchronize(scratch_ev);
-      (void)hipEventDestroy(scratch_ev);
+    for (auto& s : stream_scratch) {
+      if (s->ev) {
+        (void)hipEventSynchronize(s->ev);
+        (void)hipEventDestroy(s->ev);
+      }
+      if (s->buf) (void)hipFree(s->buf);
     }
     if (fused_ev) {
       (void)hipEventSynchronize(fused_ev);
       (void)hipEventDestroy(fused_ev);
     }
     void* ptrs[] = {d_q, d_mc, d_tw_fwd, d_tw_inv, d_ot_lo_fwd, d_ot_hi_fwd, d_ot_lo_inv, d_ot_hi_inv,
-                    d_scale, d_mu, d_bits, scratch, d_ctr};
+                    d_scale, d_mu, d_bits, d_ctr};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
   }
@@ -137,11 +172,60 @@ struct ntt_plan_s {
     return a;
   }
   int active_ot() const { return twiddle_mode == NTT_TWIDDLE_OT ? ot_stages : 0; }
+  // the paths whose data goes back to global memory after every group of stages
+  bool stage_path() const { return kernel_path == NTT_PATH_RADIX2 || kernel_path == NTT_PATH_REGISTER; }
+  // forward row stages, key product and inverse row stages in one launch (split plans whose
+  // NTT domain is the kernels' bit-reversed one)
+  bool fuses_key_rows() const { return !stage_path() && order == NTT_ORDER_BITREV; }
   bool fused_for(uint32_t n_polys) const {
     return kernel_path == NTT_PATH_FUSED && (uint64_t)n_polys * L <= kMaxFusedVectors;
   }
   static constexpr uint64_t kMaxFusedVectors = 1u << 16;
 };
+
+// Path of the tuner's flat file: $NTT_TUNE_FILE, else tune_cache.txt next to this library.
+static std::string tune_file_path() {
+  if (const char* e = std::getenv("NTT_TUNE_FILE")) return e;
+  Dl_info info{};
+  if (!dladdr(reinterpret_cast<void*>(&ntt_plan_create), &info) || !info.dli_fname) return "";
+  std::string lib = info.dli_fname;
+  const size_t slash = lib.rfind('/');
+  return (slash == std::string::npos ? std::string(".") : lib.substr(0, slash)) + "/tune_cache.txt";
+}
+
+// "<arch>:<CUs>CU" of a device, as the tuner names it.
+static std::string device_key(int dev) {
+  hipDeviceProp_t prop{};
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "";
+  std::string arch = prop.gcnArchName;
+  arch = arch.substr(0, arch.find(':'));
+  return arch + ":" + std::to_string(prop.multiProcessorCount) + "CU";
+}
+
+// Fill the option fields left at zero from the tuner's entry for this shape, if there is one.
+static bool apply_tuning(ntt_plan_opts& o, int dev, uint32_t N, const uint64_t* primes, uint32_t L) {
+  const std::string path = tune_file_path();
+  std::ifstream f(path);
+  if (path.empty() || !f) return false;
+  std::stringstream text;
+  text << f.rdbuf();
+  const auto entries = nttt::parse_tune_file(text.str());
+  uint64_t qmax = 0;
+  for (uint32_t l = 0; l < L; ++l) qmax = std::max(qmax, primes[l]);
+  uint32_t qbits = 0;
+  while (qbits < 64 && (qmax >> qbits)) ++qbits;
+  const uint32_t P = o.tune_polys > 0 ? (uint32_t)o.tune_polys : 1u;
+  const nttt::TuneEntry* e = nttt::pick_tune_entry(entries, device_key(dev), NTT_SOURCE_HASH, N, L, P, qbits);
+  if (!e) return false;
+  if (!o.twiddle_mode && !o.ot_stages && !o.ot_log2_base) {
+    o.twiddle_mode = e->twiddle_mode;
+    o.ot_stages = e->ot_stages;
+    o.ot_log2_base = e->ot_log2_base;
+  }
+  if (!o.log2_n1) o.log2_n1 = e->log2_n1;
+  if (!o.kernel_path) o.kernel_path = e->kernel_path;
+  return true;
+}
 
 static ntt_status build_plan(ntt_plan_s* p, uint32_t N, const uint64_t* primes, uint32_t L,
                              const ntt_plan_opts* opts) {
@@ -155,7 +239,21 @@ static ntt_status build_plan(ntt_plan_s* p, uint32_t N, const uint64_t* primes, 
   if (opts) o = *opts;
   for (int32_t r : o.reserved)
     if (r != 0) return fail(NTT_ERR_ARG, "reserved option fields must be zero");
-  if (o.kernel_path < 0 || o.kernel_path > 2) return fail(NTT_ERR_ARG, "kernel_path out of range");
+  const bool stage_path = o.kernel_path == NTT_PATH_RADIX2 || o.kernel_path == NTT_PATH_REGISTER;
+  if (o.use_autotune < 0 || o.use_autotune > 1 || o.tune_polys < 0)
+    return fail(NTT_ERR_ARG, "use_autotune must be 0 or 1 and tune_polys non-negative");
+  if (o.order != NTT_ORDER_BITREV && o.order != NTT_ORDER_NATURAL)
+    return fail(NTT_ERR_ARG, "order must be NTT_ORDER_BITREV or NTT_ORDER_NATURAL");
+  p->order = o.order;
+  if (o.use_autotune) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(NTT_ERR_HIP, "hipGetDevice failed");
+    p->tuned = apply_tuning(o, dev, N, primes, L);
+  }
+  if (o.kernel_path < 0 || o.kernel_path > NTT_PATH_REGISTER) return fail(NTT_ERR_ARG, "kernel_path out of range");
+  if (o.log2_radix < 0 || o.log2_radix > 5) return fail(NTT_ERR_ARG, "log2_radix must be 0..5");
+  if (o.log2_radix && o.kernel_path != NTT_PATH_REGISTER)
+    return fail(NTT_ERR_ARG, "log2_radix applies to the NTT_PATH_REGISTER path only");
   if (o.twiddle_mode < 0 || o.twiddle_mode > 2) return fail(NTT_ERR_ARG, "twiddle_mode out of range");
   if (o.ot_stages < 0 || o.ot_stages > 2) return fail(NTT_ERR_ARG, "ot_stages must be 0, 1 or 2");
   if (o.ot_log2_base < 0 || o.ot_log2_base > 16) return fail(NTT_ERR_ARG, "ot_log2_base out of range");
@@ -167,15 +265,25 @@ static ntt_status build_plan(ntt_plan_s* p, uint32_t N, const uint64_t* primes, 
   if (mode == NTT_TWIDDLE_OT && p->ot_log2_base >= p->logN)
     return fail(NTT_ERR_UNSUPPORTED, "OT needs a digit base below N");
 
-  if (o.log2_n1 == 0) {
-    p->logN1 = p->logN <= 12 ? 0 : p->logN / 2;
-  } else if (o.log2_n1 < 0) {
+  if (stage_path) {
+    // the ablation paths: table twiddles only, no column/row split
+    if (mode == NTT_TWIDDLE_OT) return fail(NTT_ERR_UNSUPPORTED, "the radix-2 and register paths take table twiddles");
+    if (o.log2_n1) return fail(NTT_ERR_ARG, "log2_n1 does not apply to the radix-2 and register paths");
     p->logN1 = 0;
+    p->log2_radix = o.kernel_path == NTT_PATH_RADIX2 ? 1 : (o.log2_radix ? o.log2_radix : 4);
+    if (o.kernel_path == NTT_PATH_REGISTER && p->log2_radix < 2)
+      return fail(NTT_ERR_ARG, "the register path takes log2_radix 2..5 (1 is NTT_PATH_RADIX2)");
   } else {
-    p->logN1 = (uint32_t)o.log2_n1;
+    if (o.log2_n1 == 0) {
+      p->logN1 = p->logN <= 12 ? 0 : p->logN / 2;
+    } else if (o.log2_n1 < 0) {
+      p->logN1 = 0;
+    } else {
+      p->logN1 = (uint32_t)o.log2_n1;
+    }
+    if (!nttk::shape_supported(p->logN, p->logN1, p->active_ot()))
+      return fail(NTT_ERR_UNSUPPORTED, "no kernels for this (N, N1, OT stages) combination");
   }
-  if (!nttk::shape_supported(p->logN, p->logN1, p->active_ot()))
-    return fail(NTT_ERR_UNSUPPORTED, "no kernels for this (N, N1, OT stages) combination");
 
   // ---- primes
   p->primes.assign(primes, primes + L);
@@ -199,7 +307,8 @@ static ntt_status build_plan(ntt_plan_s* p, uint32_t N, const uint64_t* primes, 
       return fail(NTT_ERR_UNSUPPORTED, "the fused path needs primes below 2^60 and a built N1 x N2 shape");
     // AUTO takes the split path: on gfx950 the pass-1 output of a split launch already round-trips
     // through the Infinity Cache, and the fused queue measured slower (see the design notes).
-    p->kernel_path = (o.kernel_path == NTT_PATH_FUSED && can_fuse) ? NTT_PATH_FUSED : NTT_PATH_SPLIT;
+    p->kernel_path = stage_path ? o.kernel_path
+                                : (o.kernel_path == NTT_PATH_FUSED && can_fuse) ? NTT_PATH_FUSED : NTT_PATH_SPLIT;
     if (const char* e = std::getenv("NTT_FUSED_LAG")) p->fused_lag = (uint32_t)std::max(1, std::atoi(e));
     if (const char* e = std::getenv("NTT_FUSED_GRID")) p->fused_grid = (uint32_t)std::max(1, std::atoi(e));
   }
@@ -281,11 +390,7 @@ static ntt_status build_plan(ntt_plan_s* p, uint32_t N, const uint64_t* primes, 
     c[4] = 0 - (q << 1);
     c[5] = 0 - (q << 2);
     c[6] = 0 - (q << 3);
-    uint32_t fa, fb;
-    const float fah = nttk::quot_factor_hi(q), fbh = nttk::quot_factor_lo(q);
-    std::memcpy(&fa, &fah, 4);
-    std::memcpy(&fb, &fbh, 4);
-    c[7] = (uint64_t)fa | ((uint64_t)fb << 32);
+    c[7] = nttk::quot_estimate_consts(q);
   }
 
   if (hipGetDevice(&p->device) != hipSuccess) return fail(NTT_ERR_HIP, "hipGetDevice failed");
@@ -299,8 +404,6 @@ static ntt_status build_plan(ntt_plan_s* p, uint32_t N, const uint64_t* primes, 
     if (e == hipErrorOutOfMemory) return fail(NTT_ERR_NOMEM, "device allocation of plan tables failed");
     return hip_fail(e, "uploading plan tables");
   }
-  if ((e = hipEventCreateWithFlags(&p->scratch_ev, hipEventDisableTiming)) != hipSuccess)
-    return hip_fail(e, "hipEventCreate");
   if (p->kernel_path == NTT_PATH_FUSED) {
     const size_t words = 16 + ntt_plan_s::kMaxFusedVectors;
     if ((e = hipMalloc(reinterpret_cast<void**>(&p->d_ctr), words * sizeof(uint32_t))) != hipSuccess)
@@ -310,6 +413,18 @@ static ntt_status build_plan(ntt_plan_s* p, uint32_t N, const uint64_t* primes, 
       return hip_fail(e, "hipEventCreate");
   }
   return NTT_OK;
+}
+
+// Free a plan whose last reference is gone: wait for everything queued on its device (which
+// includes every launch that reads its tables), then release its memory.
+static void plan_finalise(ntt_plan_t plan) {
+  DeviceGuard g(plan->device);
+  (void)hipDeviceSynchronize();
+  delete plan;
+}
+
+static void plan_release(ntt_plan_t plan) {
+  if (plan->rc.release()) plan_finalise(plan);
 }
 
 // Both passes in one persistent launch.  Launches of one plan share its counter block, so a
@@ -328,15 +443,42 @@ static hipError_t launch_fused(ntt_plan_t plan, uint64_t* data, uint32_t n_polys
   return hipSuccess;
 }
 
-static hipError_t transform(ntt_plan_t plan, uint64_t* data, uint32_t n_polys, bool inverse, hipStream_t st,
-                            uint32_t limbs = 0) {
-  if ((limbs == 0 || limbs == plan->L) && plan->fused_for(n_polys)) return launch_fused(plan, data, n_polys, inverse, st);
-  const PassArgs a = plan->args(data, n_polys, inverse, limbs);
+// The transform proper (bit-reversed NTT domain), without the natural-order permutation.
+// Every pass of one direction over the vectors of `a` (dense or list), by the plan's path.
+static hipError_t enqueue_direction(ntt_plan_t plan, const PassArgs& a, bool inverse, hipStream_t st) {
+  if (plan->stage_path()) return nttk::launch_stage_groups(a, plan->log2_radix, inverse, st);
   return inverse ? nttk::launch_inverse(a, plan->active_ot(), st) : nttk::launch_forward(a, plan->active_ot(), st);
 }
 
-static ntt_status check_data(ntt_plan_t plan, const void* ptr, uint32_t n_polys) {
+static hipError_t transform_brv(ntt_plan_t plan, uint64_t* data, uint32_t n_polys, bool inverse, hipStream_t st,
+                                uint32_t limbs) {
+  if ((limbs == 0 || limbs == plan->L) && plan->fused_for(n_polys)) return launch_fused(plan, data, n_polys, inverse, st);
+  return enqueue_direction(plan, plan->args(data, n_polys, inverse, limbs), inverse, st);
+}
+
+// A transform as the caller sees it: natural-order plans permute the NTT-domain slots after
+// the forward transform and before the inverse.
+static hipError_t transform(ntt_plan_t plan, uint64_t* data, uint32_t n_polys, bool inverse, hipStream_t st,
+                            uint32_t limbs = 0) {
+  hipError_t e;
+  const bool nat = plan->order == NTT_ORDER_NATURAL;
+  if (nat && inverse && (e = nttk::launch_brv_permute(plan->args(data, n_polys, true, limbs), st)) != hipSuccess)
+    return e;
+  if ((e = transform_brv(plan, data, n_polys, inverse, st, limbs)) != hipSuccess) return e;
+  if (nat && !inverse && (e = nttk::launch_brv_permute(plan->args(data, n_polys, false, limbs), st)) != hipSuccess)
+    return e;
+  return hipSuccess;
+}
+
+static ntt_status check_plan(ntt_plan_t plan) {
   if (!plan) return fail(NTT_ERR_ARG, "plan is NULL");
+  if (plan->rc.owner_gone.load(std::memory_order_relaxed))
+    return fail(NTT_ERR_ARG, "plan was destroyed (only the batches that name it may still run it)");
+  return NTT_OK;
+}
+
+static ntt_status check_data(ntt_plan_t plan, const void* ptr, uint32_t n_polys) {
+  if (ntt_status s = check_plan(plan)) return s;
   if (!ptr) return fail(NTT_ERR_ARG, "data pointer is NULL");
   if (reinterpret_cast<uintptr_t>(ptr) & 15) return fail(NTT_ERR_ARG, "data pointer must be 16-byte aligned");
   if (n_polys == 0) return fail(NTT_ERR_ARG, "n_polys must be at least 1");
@@ -344,6 +486,64 @@ static ntt_status check_data(ntt_plan_t plan, const void* ptr, uint32_t n_polys)
   const uint64_t n_vec = (uint64_t)n_polys * plan->L;
   if (n_vec * ((uint64_t)plan->N / 16 + 1) >= (1ull << 31)) return fail(NTT_ERR_ARG, "batch too large for one launch");
   return NTT_OK;
+}
+
+static ntt_status check_product(ntt_plan_t plan, const uint64_t* d_a, const uint64_t* d_b, const uint64_t* d_c,
+                                uint32_t n_polys) {
+  ntt_status s;
+  if ((s = check_data(plan, d_a, n_polys)) != NTT_OK || (s = check_data(plan, d_b, n_polys)) != NTT_OK ||
+      (s = check_data(plan, d_c, n_polys)) != NTT_OK)
+    return s;
+  if (d_c == d_b) return fail(NTT_ERR_ARG, "d_c must not alias d_b");
+  return NTT_OK;
+}
+
+// The launches of c = a * b with NTT(b) placed in `tmp` (n_polys*L*N words of device memory
+// that nothing else uses until they complete).  Split plans: NTT(b) into tmp (first pass out
+// of place), a's forward column pass out of place into c, the row passes with the product by
+// NTT(b) in one launch, and the inverse column pass; a single-pass size does the whole
+// product in that launch.  Fused-path plans: copies, both transforms, the element-wise
+// product and the inverse as separate launches.  Allocates nothing.
+static hipError_t polymul_enqueue(ntt_plan_t plan, const uint64_t* d_a, const uint64_t* d_b, uint64_t* d_c,
+                                  uint32_t n_polys, uint64_t* tmp, hipStream_t st) {
+  hipError_t e;
+  const int ot = plan->active_ot();
+  if (plan->kernel_path == NTT_PATH_SPLIT) {
+    PassArgs fb = plan->args(tmp, n_polys, false);
+    PassArgs fa = plan->args(d_c, n_polys, false);
+    const PassArgs ia = plan->args(d_c, n_polys, true);
+    fb.src = d_b;
+    fa.src = d_a;
+    fa.key = tmp;
+    if (plan->logN1) {
+      PassArgs fa_col = fa;
+      fa_col.key = nullptr;
+      fa.src = nullptr;   // the row launch reads c, which the column pass wrote
+      PassArgs fb_row = fb;
+      fb_row.src = nullptr;
+      if ((e = nttk::launch_forward_pass(fb, ot, 0, st)) != hipSuccess ||
+          (e = nttk::launch_forward_pass(fb_row, ot, 1, st)) != hipSuccess ||
+          (e = nttk::launch_forward_pass(fa_col, ot, 0, st)) != hipSuccess ||
+          (e = nttk::launch_mul_rows(fa, ia, ot, st)) != hipSuccess ||
+          (e = nttk::launch_inverse_pass(ia, ot, 1, st)) != hipSuccess)
+        return e;
+      return hipSuccess;
+    }
+    if ((e = nttk::launch_forward_pass(fb, ot, 0, st)) != hipSuccess ||
+        (e = nttk::launch_mul_rows(fa, ia, ot, st)) != hipSuccess)
+      return e;
+    return hipSuccess;
+  }
+  const size_t bytes = (size_t)n_polys * plan->L * plan->N * sizeof(uint64_t);
+  if (d_c != d_a && (e = hipMemcpyAsync(d_c, d_a, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(tmp, d_b, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) return e;
+  if ((e = transform_brv(plan, d_c, n_polys, false, st, 0)) != hipSuccess ||
+      (e = transform_brv(plan, tmp, n_polys, false, st, 0)) != hipSuccess ||
+      (e = nttk::launch_pointwise(d_c, tmp, d_c, plan->d_q, plan->d_mu, plan->d_bits,
+                                  (uint64_t)n_polys * plan->L * plan->N, plan->logN, plan->L, st)) != hipSuccess ||
+      (e = transform_brv(plan, d_c, n_polys, true, st, 0)) != hipSuccess)
+    return e;
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------- batches
@@ -356,6 +556,7 @@ struct ntt_batch_s {
   };
   std::vector<ntt_job> jobs;
   std::vector<Group> groups;
+  std::vector<ntt_plan_t> held;         // one reference on every distinct plan of the jobs
   int device = 0;
   nttk::VecDesc* d_desc = nullptr;      // descriptor arena (device)
   nttk::VecDesc* h_desc = nullptr;      // pinned staging copy of the arena
@@ -384,6 +585,15 @@ struct ntt_batch_s {
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
     if (d_desc) (void)hipFree(d_desc);
     if (h_desc) (void)hipHostFree(h_desc);
+    hold({});
+  }
+
+  // Hold references on exactly `plans` (the distinct plans of the current jobs); a plan whose
+  // last reference this drops is finalised.
+  void hold(const std::vector<ntt_plan_t>& plans) {
+    const auto last = nttl::rehold(held, plans, [](ntt_plan_t p) -> nttl::RefCount& { return p->rc; });
+    held = plans;
+    for (ntt_plan_t p : last) plan_finalise(p);
   }
 
   const nttk::VecDesc* at(uint64_t off) const { return d_desc + off; }
@@ -424,7 +634,10 @@ struct ntt_batch_s {
         const uint64_t n = inv ? g.n_inv : g.n_fwd;
         if (n) {
           const PassArgs a = list_args(g, inv ? g.off_inv : g.off_fwd, n, inv);
-          if ((e = inv ? nttk::launch_inverse(a, ot, st) : nttk::launch_forward(a, ot, st)) != hipSuccess) return e;
+          const bool nat = g.plan->order == NTT_ORDER_NATURAL;
+          if (nat && inv && (e = nttk::launch_brv_permute(a, st)) != hipSuccess) return e;
+          if ((e = enqueue_direction(g.plan, a, inv, st)) != hipSuccess) return e;
+          if (nat && !inv && (e = nttk::launch_brv_permute(a, st)) != hipSuccess) return e;
         }
         if (g.n_full && split) {
           const PassArgs a = list_args(g, g.off_full, g.n_full, inv);
@@ -446,6 +659,8 @@ static ntt_status plan_batch(ntt_batch_s* b, const ntt_job* jobs, uint32_t n_job
   for (uint32_t j = 0; j < n_jobs; ++j) {
     const ntt_job& job = js[j];
     if (!job.plan || !job.d_data) return fail(NTT_ERR_ARG, "job " + std::to_string(j) + ": NULL plan or data");
+    if (job.plan->rc.owner_gone.load(std::memory_order_relaxed))
+      return fail(NTT_ERR_ARG, "job " + std::to_string(j) + ": plan was destroyed");
     if (reinterpret_cast<uintptr_t>(job.d_data) & 15) return fail(NTT_ERR_ARG, "job data must be 16-byte aligned");
     if (job.n_polys == 0 || job.n_limbs > job.plan->L || job.reserved)
       return fail(NTT_ERR_ARG, "job " + std::to_string(j) + ": bad n_polys, n_limbs or reserved field");
@@ -471,7 +686,9 @@ static ntt_status plan_batch(ntt_batch_s* b, const ntt_job* jobs, uint32_t n_job
         for (uint32_t p = 0; p < job.n_polys; ++p) {
           nttk::VecDesc d{job.d_data + ((uint64_t)p * lim + l) * plan->N, nullptr, l, 0};
           if (job.op & NTT_OP_MULKEY) d.key = job.d_key + (uint64_t)l * plan->N;
-          if (job.op == (NTT_OP_FORWARD | NTT_OP_MULKEY | NTT_OP_INVERSE)) {
+          // forward, key product and inverse in the fused row launch; natural-order plans take
+          // their keys in natural order, so they run the three steps as separate lists instead
+          if (job.op == (NTT_OP_FORWARD | NTT_OP_MULKEY | NTT_OP_INVERSE) && plan->fuses_key_rows()) {
             full.push_back(d);
             continue;
           }
@@ -499,6 +716,7 @@ static ntt_status plan_batch(ntt_batch_s* b, const ntt_job* jobs, uint32_t n_job
   }
   b->jobs.swap(js);
   b->groups.swap(groups);
+  b->hold(plans);
   return NTT_OK;
 }
 
@@ -563,8 +781,15 @@ ntt_status ntt_plan_create(ntt_plan_t* out, uint32_t N, const uint64_t* primes, 
 ntt_status ntt_plan_destroy(ntt_plan_t plan) {
   try {
     if (!plan) return NTT_OK;
-    DeviceGuard g(plan->device);
-    delete plan;
+    switch (plan->rc.release_owner()) {
+      case nttl::RefCount::kAlreadyGone:
+        return fail(NTT_ERR_ARG, "plan destroyed twice");
+      case nttl::RefCount::kLast:
+        plan_finalise(plan);
+        break;
+      case nttl::RefCount::kStillHeld:   // a batch still names it: freed when the last one lets go
+        break;
+    }
     return NTT_OK;
   } catch (...) {
     return fail(NTT_ERR_ARG, "unexpected failure in ntt_plan_destroy");
@@ -572,14 +797,25 @@ ntt_status ntt_plan_destroy(ntt_plan_t plan) {
 }
 
 ntt_status ntt_plan_get_roots(ntt_plan_t plan, uint64_t* psi_out) {
-  if (!plan || !psi_out) return fail(NTT_ERR_ARG, "NULL argument");
+  if (ntt_status s = check_plan(plan)) return s;
+  if (!psi_out) return fail(NTT_ERR_ARG, "NULL argument");
   std::memcpy(psi_out, plan->psis.data(), plan->L * sizeof(uint64_t));
   return NTT_OK;
 }
 
+int32_t ntt_plan_log2_radix(ntt_plan_t plan) {
+  if (check_plan(plan) != NTT_OK) return -1;
+  return plan->log2_radix;
+}
+
+int32_t ntt_plan_order(ntt_plan_t plan) {
+  if (check_plan(plan) != NTT_OK) return -1;
+  return plan->order;
+}
+
 ntt_status ntt_plan_get_info(ntt_plan_t plan, uint32_t* N, uint32_t* L, uint32_t* log2_n1, int32_t* twiddle_mode,
                              int32_t* ot_stages, int32_t* kernel_path) {
-  if (!plan) return fail(NTT_ERR_ARG, "plan is NULL");
+  if (ntt_status s = check_plan(plan)) return s;
   if (N) *N = plan->N;
   if (L) *L = plan->L;
   if (log2_n1) *log2_n1 = plan->logN1;
@@ -602,8 +838,20 @@ ntt_status ntt_forward(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, void
   }
 }
 
+int32_t ntt_plan_tuned(ntt_plan_t plan) {
+  if (check_plan(plan) != NTT_OK) return -1;
+  return plan->tuned ? 1 : 0;
+}
+
+// Kernels of the transform proper (without the natural-order permutation).
+static uint32_t core_passes(ntt_plan_t plan) {
+  if (plan->stage_path()) return nttk::stage_group_count(plan->logN, plan->log2_radix);
+  return (plan->logN1 && plan->kernel_path != NTT_PATH_FUSED) ? 2u : 1u;
+}
+
 uint32_t ntt_plan_num_passes(ntt_plan_t plan) {
-  return plan ? ((plan->logN1 && plan->kernel_path != NTT_PATH_FUSED) ? 2u : 1u) : 0u;
+  if (check_plan(plan) != NTT_OK) return 0u;
+  return core_passes(plan) + (plan->order == NTT_ORDER_NATURAL ? 1u : 0u);
 }
 
 static ntt_status run_pass(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, uint32_t pass, void* stream,
@@ -617,9 +865,20 @@ static ntt_status run_pass(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, 
     const PassArgs a = plan->args(d_data, n_polys, inverse);
     const hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e;
+    // natural-order plans: the permutation is the last forward pass and the first inverse pass
+    if (plan->order == NTT_ORDER_NATURAL) {
+      const uint32_t perm_pass = inverse ? 0u : core_passes(plan);
+      if (pass == perm_pass) {
+        e = nttk::launch_brv_permute(a, st);
+        return e == hipSuccess ? NTT_OK : hip_fail(e, "pass launch");
+      }
+      if (inverse) --pass;
+    }
     if (plan->kernel_path == NTT_PATH_FUSED) {
       if (!plan->fused_for(n_polys)) return fail(NTT_ERR_ARG, "batch too large for the fused path's counters");
       e = launch_fused(plan, d_data, n_polys, inverse, st);
+    } else if (plan->stage_path()) {
+      e = nttk::launch_stage_group(a, plan->log2_radix, inverse, pass, st);
     } else {
       e = inverse ? nttk::launch_inverse_pass(a, plan->active_ot(), (int)pass, st)
                   : nttk::launch_forward_pass(a, plan->active_ot(), (int)pass, st);
@@ -672,76 +931,39 @@ ntt_status ntt_pointwise_mul(ntt_plan_t plan, const uint64_t* d_a, const uint64_
 ntt_status ntt_polymul_negacyclic(ntt_plan_t plan, const uint64_t* d_a, const uint64_t* d_b, uint64_t* d_c,
                                   uint32_t n_polys, void* stream) {
   try {
-    ntt_status s;
-    if ((s = check_data(plan, d_a, n_polys)) != NTT_OK || (s = check_data(plan, d_b, n_polys)) != NTT_OK ||
-        (s = check_data(plan, d_c, n_polys)) != NTT_OK)
-      return s;
-    if (d_c == d_b) return fail(NTT_ERR_ARG, "d_c must not alias d_b");
+    ntt_status s = check_product(plan, d_a, d_b, d_c, n_polys);
+    if (s != NTT_OK) return s;
     DeviceGuard g(plan->device);
     if (!g.ok) return fail(NTT_ERR_HIP, "cannot select the plan's device");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const size_t bytes = (size_t)n_polys * plan->L * plan->N * sizeof(uint64_t);
 
-    std::lock_guard<std::mutex> lk(plan->scratch_mu);
+    ntt_plan_s::StreamScratch* sc = plan->scratch_for(st);
+    std::lock_guard<std::mutex> lk(sc->mu);
     hipError_t e;
-    if (plan->scratch_bytes < bytes) {
-      if (plan->scratch_pending && (e = hipEventSynchronize(plan->scratch_ev)) != hipSuccess)
-        return hip_fail(e, "waiting for scratch");
-      if (plan->scratch) (void)hipFree(plan->scratch);
-      plan->scratch = nullptr;
-      plan->scratch_bytes = 0;
-      if ((e = hipMalloc(reinterpret_cast<void**>(&plan->scratch), bytes)) != hipSuccess)
+    if (!sc->ev && (e = hipEventCreateWithFlags(&sc->ev, hipEventDisableTiming)) != hipSuccess) {
+      sc->ev = nullptr;
+      return hip_fail(e, "hipEventCreate");
+    }
+    if (sc->bytes < bytes) {
+      // the old buffer may still feed the last product enqueued on this stream
+      if (sc->pending && (e = hipEventSynchronize(sc->ev)) != hipSuccess) return hip_fail(e, "waiting for scratch");
+      if (sc->buf) (void)hipFree(sc->buf);
+      sc->buf = nullptr;
+      sc->bytes = 0;
+      sc->pending = false;
+      if ((e = hipMalloc(reinterpret_cast<void**>(&sc->buf), bytes)) != hipSuccess)
         return e == hipErrorOutOfMemory ? fail(NTT_ERR_NOMEM, "scratch allocation failed")
                                         : hip_fail(e, "scratch allocation");
-      plan->scratch_bytes = bytes;
-      plan->scratch_pending = false;
+      sc->bytes = bytes;
     }
-    if (plan->scratch_pending && (e = hipStreamWaitEvent(st, plan->scratch_ev, 0)) != hipSuccess)
-      return hip_fail(e, "ordering scratch use");
-    uint64_t* tmp = plan->scratch;
-    const int ot = plan->active_ot();
-    if (plan->kernel_path == NTT_PATH_SPLIT) {
-      // NTT(b) into the scratch (first pass out of place), then a: its forward column pass
-      // out of place into c, the row passes with the product by NTT(b) in one launch, and
-      // the inverse column pass.  A single-pass size does the whole product in that launch.
-      PassArgs fb = plan->args(tmp, n_polys, false);
-      PassArgs fa = plan->args(d_c, n_polys, false);
-      const PassArgs ia = plan->args(d_c, n_polys, true);
-      fb.src = d_b;
-      fa.src = d_a;
-      fa.key = tmp;
-      if (plan->logN1) {
-        PassArgs fa_col = fa;
-        fa_col.key = nullptr;
-        fa.src = nullptr;   // the row launch reads c, which the column pass wrote
-        PassArgs fb_row = fb;
-        fb_row.src = nullptr;
-        if ((e = nttk::launch_forward_pass(fb, ot, 0, st)) != hipSuccess ||
-            (e = nttk::launch_forward_pass(fb_row, ot, 1, st)) != hipSuccess ||
-            (e = nttk::launch_forward_pass(fa_col, ot, 0, st)) != hipSuccess ||
-            (e = nttk::launch_mul_rows(fa, ia, ot, st)) != hipSuccess ||
-            (e = nttk::launch_inverse_pass(ia, ot, 1, st)) != hipSuccess)
-          return hip_fail(e, "ntt_polymul_negacyclic launch");
-      } else if ((e = nttk::launch_forward_pass(fb, ot, 0, st)) != hipSuccess ||
-                 (e = nttk::launch_mul_rows(fa, ia, ot, st)) != hipSuccess) {
-        return hip_fail(e, "ntt_polymul_negacyclic launch");
-      }
-    } else {
-      if (d_c != d_a && (e = hipMemcpyAsync(d_c, d_a, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess)
-        return hip_fail(e, "copying a");
-      if ((e = hipMemcpyAsync(tmp, d_b, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess)
-        return hip_fail(e, "copying b");
-      if ((e = transform(plan, d_c, n_polys, false, st)) != hipSuccess ||
-          (e = transform(plan, tmp, n_polys, false, st)) != hipSuccess ||
-          (e = nttk::launch_pointwise(d_c, tmp, d_c, plan->d_q, plan->d_mu, plan->d_bits,
-                                      (uint64_t)n_polys * plan->L * plan->N, plan->logN, plan->L, st)) !=
-              hipSuccess ||
-          (e = transform(plan, d_c, n_polys, true, st)) != hipSuccess)
-        return hip_fail(e, "ntt_polymul_negacyclic launch");
-    }
-    if ((e = hipEventRecord(plan->scratch_ev, st)) != hipSuccess) return hip_fail(e, "recording scratch event");
-    plan->scratch_pending = true;
+    if ((e = polymul_enqueue(plan, d_a, d_b, d_c, n_polys, sc->buf, st)) != hipSuccess)
+      return hip_fail(e, "ntt_polymul_negacyclic launch");
+    if ((e = hipEventRecord(sc->ev, st)) != hipSuccess) return hip_fail(e, "recording scratch event");
+    sc->pending = true;
     return NTT_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(NTT_ERR_NOMEM, "host allocation failed");
   } catch (...) {
     return fail(NTT_ERR_ARG, "unexpected failure in ntt_polymul_negacyclic");
   }
@@ -788,6 +1010,7 @@ ntt_status ntt_batch_assign(ntt_batch_t b, const ntt_job* jobs, uint32_t n_jobs,
       b->jobs.clear();
       b->groups.clear();
       b->drop_graph();
+      b->hold({});
     }
     return s;
   } catch (const std::bad_alloc&) {
@@ -826,16 +1049,27 @@ ntt_status ntt_batch_run(ntt_batch_t b, int32_t mode, void* stream) {
       e = b->grouped(st);
     } else if (mode == NTT_BATCH_GRAPH) {
       if (!b->exec) {
-        if ((e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking)) != hipSuccess)
+        // the private capture stream lives as long as the batch: reassigning the jobs drops
+        // the graph but keeps the stream
+        if (!b->capture_stream &&
+            (e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking)) != hipSuccess) {
+          b->capture_stream = nullptr;
           return hip_fail(e, "creating the capture stream");
+        }
+        b->drop_graph();
         if ((e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
           return hip_fail(e, "hipStreamBeginCapture");
         const hipError_t le = b->grouped(b->capture_stream);
         e = hipStreamEndCapture(b->capture_stream, &b->graph);
-        if (le != hipSuccess) return hip_fail(le, "capturing the batch");
-        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-        if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess)
+        if (le != hipSuccess || e != hipSuccess) {
+          b->drop_graph();   // a partial graph is never kept or replayed
+          return hip_fail(le != hipSuccess ? le : e, le != hipSuccess ? "capturing the batch" : "hipStreamEndCapture");
+        }
+        if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess) {
+          b->exec = nullptr;
+          b->drop_graph();
           return hip_fail(e, "hipGraphInstantiate");
+        }
       }
       e = hipGraphLaunch(b->exec, st);
     } else {

@@ -32,6 +32,17 @@ bool fused_supported(uint32_t logN, uint32_t logN1, int ot_stages);
 hipError_t launch_fused(const PassArgs& a, int ot_stages, bool inverse, uint32_t* ctr, uint32_t n_polys,
                         uint32_t lag, uint32_t max_grid, hipStream_t st);
 
+// Transforms that keep the data in global memory between launches (stages.hip): one launch
+// per group of log2_radix consecutive stages (1 = radix-2, one launch per stage).  Group g
+// counts in execution order (the inverse runs the forward groups backwards).
+uint32_t stage_group_count(uint32_t logN, int log2_radix);
+hipError_t launch_stage_group(const PassArgs& a, int log2_radix, bool inverse, uint32_t g, hipStream_t st);
+hipError_t launch_stage_groups(const PassArgs& a, int log2_radix, bool inverse, hipStream_t st);
+
+// In-place bit-reversal permutation of every vector described by `a` (slot i <-> slot
+// brv(i)): turns the forward transform's bit-reversed output into natural order and back.
+hipError_t launch_brv_permute(const PassArgs& a, hipStream_t st);
+
 // Every vector of a list times its key vector, in place (Barrett products).
 hipError_t launch_pointwise_list(const VecDesc* vecs, uint64_t n_vec, uint32_t logN, const uint64_t* qs,
                                  const uint64_t* mus, const uint32_t* bits, hipStream_t st);

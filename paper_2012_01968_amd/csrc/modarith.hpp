@@ -35,22 +35,25 @@ struct Tw {  // a twiddle and its Shoup companion, stored as one 16-byte entry
   uint64_t w, wb;
 };
 
-// Quotient-estimate factors 2^32/q and 1/q, rounded to float after scaling by (1 - 2^-20):
-// the bias keeps every float estimate of x/q at or below the true value (see fwd_final).
-__host__ __device__ inline float quot_factor_hi(uint64_t q) {
-  return (float)(4294967296.0 / (double)q * (1.0 - 0x1p-20));
+// Integer estimate of k = floor(x / q) for x < 16q (the forward final reduction), with
+// s = bitlen(q) >= 3: t = floor(x / 2^(s-3)) < 2^7 and m = floor(2^(s+6) / q) <= 2^7, so
+// t * m < 2^14 fits a 24-bit multiply, and est = floor(t * m / 2^9) is k or k - 1.
+//   est <= t 2^(s-3) / q <= x / q, so est <= k;
+//   x/q - est < (x - t 2^(s-3))/q + t (2^(s-3)/q - m/2^9) + 1 < 1/4 + 1/4 + 1, so est >= k - 1.
+// The two per-prime constants are packed as m | (s - 3) << 32.
+__host__ inline uint64_t quot_estimate_consts(uint64_t q) {
+  uint32_t s = 0;
+  while (s < 64 && (q >> s)) ++s;
+  const uint64_t m = (uint64_t)(((unsigned __int128)1 << (s + 6)) / q);
+  return m | ((uint64_t)(s - 3) << 32);
 }
-__host__ __device__ inline float quot_factor_lo(uint64_t q) { return (float)(1.0 / (double)q * (1.0 - 0x1p-20)); }
 
 struct Mod {  // per-prime constants
   uint64_t q, q2, q4, q8, nq, nq2, nq4, nq8;  // q, 2q, 4q, 8q, and the negatives mod 2^64 of q, 2q, 4q, 8q
-  float fa, fb;                           // quot_factor_hi(q), quot_factor_lo(q)
-  __device__ __forceinline__ explicit Mod(uint64_t p)
-      : q(p), q2(p << 1), q4(p << 2), q8(p << 3), nq(0 - p), nq2(0 - (p << 1)), nq4(0 - (p << 2)), nq8(0 - (p << 3)),
-        fa(quot_factor_hi(p)), fb(quot_factor_lo(p)) {}
+  uint32_t qm, qsh;                       // quotient-estimate multiplier and shift (quot_estimate_consts)
   Mod() = default;
-  // From a per-prime constant row {q, 2q, 4q, -q, -2q, -4q, -8q, f} (negatives mod 2^64), f
-  // holding the bits of quot_factor_hi(q) in its low and quot_factor_lo(q) in its high word.
+  // From a per-prime constant row {q, 2q, 4q, -q, -2q, -4q, -8q, c} (negatives mod 2^64), c
+  // = quot_estimate_consts(q).
   template <typename Ptr>
   static __device__ __forceinline__ Mod load(Ptr c) {
     Mod m;
@@ -63,8 +66,8 @@ struct Mod {  // per-prime constants
     m.nq4 = c[5];
     m.nq8 = c[6];
     const uint64_t f = c[7];
-    m.fa = __uint_as_float((uint32_t)f);
-    m.fb = __uint_as_float((uint32_t)(f >> 32));
+    m.qm = (uint32_t)f;
+    m.qsh = (uint32_t)(f >> 32);
     return m;
   }
 };
@@ -232,14 +235,12 @@ struct Arith<true> {
     X = mul(s, n, m);
     Y = mul(d, wn, m);
   }
-  // [0, 16q) -> [0, q).  k = floor(x / q) < 16 is estimated in float from the two halves
-  // of x with the low-biased factors of Mod: every rounding error is far below the 2^-20
-  // bias, so the estimate is k or k - 1, x - estimate * q lies in [0, 2q), and one
-  // conditional subtraction finishes.
+  // [0, 16q) -> [0, q).  k = floor(x / q) < 16 is estimated from the top bits of x and the
+  // per-prime multiplier (quot_estimate_consts): the estimate is k or k - 1, so x - est * q
+  // lies in [0, 2q) and one conditional subtraction finishes (four before).
   static __device__ __forceinline__ uint64_t fwd_final(uint64_t x, const Mod& m) {
-    const float lo = __fmul_rn(__uint2float_rn((uint32_t)x), m.fb);
-    const float e = __fmaf_rn(__uint2float_rn((uint32_t)(x >> 32)), m.fa, lo);
-    const uint32_t k = __float2uint_rz(e);
+    const uint32_t t = (uint32_t)(x >> m.qsh);
+    const uint32_t k = __umul24(t, m.qm) >> 9;
     return csub_sign(x + (uint64_t)k * m.nq, m.nq);
   }
   static __device__ __forceinline__ uint64_t inv_final(uint64_t x, const Mod& m) {

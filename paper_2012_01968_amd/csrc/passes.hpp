@@ -53,7 +53,8 @@ struct PassArgs {
   const uint64_t* key;
   const uint64_t* mu;
   const uint32_t* bits;
-  // [L][8] per-prime constants {q, 2q, 4q, -q, -2q, -4q, -8q, float factors} (Mod::load).
+  // [L][8] per-prime constants {q, 2q, 4q, -q, -2q, -4q, -8q, quotient-estimate constants}
+  // (Mod::load).
   // Loaded rather than derived from q in the kernel, so that the compiler adds them as
   // 64-bit operands instead of re-deriving them from q's halves.
   const uint64_t* mc;

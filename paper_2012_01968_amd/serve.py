@@ -3,7 +3,7 @@
 A request is one ciphertext-shaped job: ``polys`` polynomials of ``L`` limbs at ring
 degree ``N`` that need the forward transform, a product with a key polynomial kept
 resident on the device in the NTT domain, and the inverse transform (the NTT-based
-negacyclic product of Sec. II, applied to every RNS limb).  The loop:
+negacyclic product of Section III-A, applied to every RNS limb).  The loop:
 
 * admits arrived requests in FIFO order while their footprint (the bytes of their
   residues) fits in a fixed device arena; twiddle tables and keys are resident and not

@@ -6,17 +6,17 @@
 //   2. Cooley-Tukey butterflies that reduce X by 8q only in even stages keep values below 16q,
 //      and every conditional subtraction has |x - m| < 2^63 (the sign test is valid);
 //   3. the forward final reduction (8q, 4q, 2q, q) maps [0, 16q) onto [0, q);
-//   4. so does the quotient-estimate form: k = floor(x / q) estimated in float from the two
-//      32-bit halves of x with factors 2^32/q and 1/q scaled by (1 - 2^-20) before rounding,
-//      then x - k*q (in [0, 2q) when the estimate is k or k - 1) and one subtraction of q.
-//      The float steps (round-to-nearest conversions, a product, a fused multiply-add,
-//      truncation) are IEEE single precision on both the host and the GPU;
+//   4. so does the quotient-estimate form: k = floor(x / q) estimated in integers as
+//      ((x >> (s - 3)) * floor(2^(s+6) / q)) >> 9 with s = bitlen(q) (a product below 2^14,
+//      one 24-bit multiply on the GPU), then x - k*q (in [0, 2q) when the estimate is k or
+//      k - 1) and one subtraction of q.  QSHIFT, QEXTRA and QROUNDUP plant mistakes in it
+//      (a shift of s - 2, a multiplier scaled by 2^7 instead of 2^6 with the same final
+//      shift, a multiplier rounded up); each must make this check fail;
 //   5. Gentleman-Sande register steps (8 values, up to 3 stages) with per-register bounds:
 //      inputs below IN_B q, a sum reduced by 8q only when its inputs' bound is above 4q, the
 //      difference offset by the inputs' bound, products below 4q; every value stays below 8q,
 //      and a chain of steps ending in the scaled stage and the final reduction is canonical
 //      and congruent to the exact transform's arithmetic.
-#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <random>
@@ -48,12 +48,24 @@ static uint64_t csub(uint64_t x, uint64_t m, uint64_t q) {
   return (int64_t)d < 0 ? x : d;
 }
 
+#ifndef QSHIFT
+#define QSHIFT 3
+#endif
+#ifndef QEXTRA
+#define QEXTRA 6
+#endif
+#ifndef QROUNDUP
+#define QROUNDUP 0
+#endif
+
 static uint64_t quotient_final(uint64_t x, uint64_t q) {
-  const float fa = (float)(4294967296.0 / (double)q * (1.0 - 0x1p-20));
-  const float fb = (float)(1.0 / (double)q * (1.0 - 0x1p-20));
-  volatile float lo = (float)(uint32_t)x * fb;   // a separate rounding, as on the GPU
-  const float e = std::fmaf((float)(uint32_t)(x >> 32), fa, lo);
-  const uint32_t k = (uint32_t)e;                // truncation
+  uint32_t s = 0;
+  while (s < 64 && (q >> s)) ++s;
+  const u128 num = (u128)1 << (s + QEXTRA);
+  const uint64_t m = (uint64_t)(num / q + (QROUNDUP && num % q ? 1 : 0));
+  const uint64_t t = x >> (s - QSHIFT);
+  if (t >= 128 || m > 128) fail("quotient estimate operands exceed 2^7", q, x, m);
+  const uint32_t k = (uint32_t)((t * m) >> 9);
   if (k > 15) fail("quotient estimate above 15", q, x, k);
   const uint64_t r = x - (uint64_t)k * q;        // modulo 2^64
   if (r >= 2 * q) fail("x - k*q outside [0, 2q)", q, x, k);
@@ -133,10 +145,11 @@ int main() {
   }
   // claim 4 at every multiple of q below 16q (and just around it), for random and extreme q
   {
-    std::vector<uint64_t> qs = {3, 5, 7, (1ull << 31) - 1, (1ull << 32) + 15, (1ull << 59) + 1,
+    // moduli of at least 3 bits: an NTT prime is 1 mod 2N with N >= 2, so q >= 5
+    std::vector<uint64_t> qs = {5, 7, (1ull << 31) - 1, (1ull << 32) + 15, (1ull << 59) + 1,
                                 (1ull << 59) + 55, (1ull << 60) - 93, (1ull << 60) - 1};
     for (int i = 0; i < 20000; ++i) {
-      const int bits = 2 + (int)(g() % 59);   // 2..60-bit odd moduli
+      const int bits = 3 + (int)(g() % 58);   // 3..60-bit odd moduli
       uint64_t q = (g() >> (64 - bits)) | (1ull << (bits - 1)) | 1;
       if (q >= (1ull << 60)) q = (1ull << 60) - 1;
       if (q > 2) qs.push_back(q);

@@ -51,7 +51,9 @@ def test_status_strings(lib):
 class _Opts(ctypes.Structure):
     _fields_ = [("twiddle_mode", ctypes.c_int32), ("ot_stages", ctypes.c_int32),
                 ("ot_log2_base", ctypes.c_int32), ("log2_n1", ctypes.c_int32),
-                ("kernel_path", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("kernel_path", ctypes.c_int32), ("use_autotune", ctypes.c_int32),
+                ("tune_polys", ctypes.c_int32), ("order", ctypes.c_int32), ("log2_radix", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 def _create(lib, N, primes, opts=None):
@@ -76,14 +78,26 @@ def test_argument_errors_are_synchronous(lib):
     assert _create(lib, 1 << 10, [1 + (1 << 11) * 3 * 5]) == (-3, None)  # 30721 = 31*991: composite, 1 mod 2N
     assert _create(lib, 1 << 10, []) == (-1, None)
     o = _Opts()
-    o.reserved[0] = 1
+    o.reserved[1] = 1
     assert _create(lib, 1 << 10, [q], o) == (-1, None)
+    o = _Opts(0, 0, 0, 0, 0, 0, 0, 2)
+    assert _create(lib, 1 << 10, [q], o) == (-1, None)             # order is BITREV or NATURAL
+    o = _Opts(0, 0, 0, 0, 0, 2)
+    assert _create(lib, 1 << 10, [q], o) == (-1, None)             # use_autotune is 0 or 1
+    o = _Opts(0, 0, 0, 0, 0, 1, -1)
+    assert _create(lib, 1 << 10, [q], o) == (-1, None)             # negative tune_polys
     o = _Opts(2, 2, 10, 0)
     assert _create(lib, 1 << 10, [q], o) == (-6, None)             # OT base must be below N
     o = _Opts(0, 0, 0, 11)
     assert _create(lib, 1 << 16, [q], o) == (-6, None)             # no column pass of 2^11
-    o = _Opts(0, 0, 0, 0, 3)
+    o = _Opts(0, 0, 0, 0, 5)
     assert _create(lib, 1 << 16, [q], o) == (-1, None)             # kernel_path out of range
+    o = _Opts(0, 0, 0, 0, 4, 0, 0, 0, 1)
+    assert _create(lib, 1 << 16, [q], o) == (-1, None)             # register path: radix 2^2 .. 2^5
+    o = _Opts(0, 0, 0, 0, 1, 0, 0, 0, 3)
+    assert _create(lib, 1 << 16, [q], o) == (-1, None)             # log2_radix only with the register path
+    o = _Opts(2, 2, 10, 0, 3)
+    assert _create(lib, 1 << 16, [q], o) == (-6, None)             # radix-2 path: table twiddles only
     o = _Opts(0, 0, 0, 9, 2)
     assert _create(lib, 1 << 16, [q], o) == (-6, None)             # no fused 2^9 x 2^7 shape
     lib.ntt_forward.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p]

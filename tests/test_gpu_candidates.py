@@ -1,0 +1,86 @@
+"""Every plan the tuner can choose, against the CPU oracle.
+
+For each transform size N = 2^1 .. 2^17 and two prime widths (60-bit primes take the
+estimated-quotient arithmetic, 62-bit primes the exact one), every option set that
+``autotune.candidates(N)`` enumerates is built and its forward transform (Algorithm 1),
+its inverse and its negacyclic product (Section III-A) are compared element by element
+with the oracle on the same seeded inputs.  This covers every split N1 x N2 (including the
+2^11-point rows of N1 = 2^6 at N = 2^17), the key-product row kernel at every row length,
+every OT depth and digit base, and the fused launch where its shape exists.  Tolerance 0:
+the arithmetic is exact.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+ntt = pytest.importorskip("paper_2012_01968_amd")
+from paper_2012_01968_amd import autotune  # noqa: E402
+
+THREADS = min(16, os.cpu_count() or 1)
+L, P = 3, 2
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to("cuda")
+
+
+def host(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+@pytest.mark.parametrize("bits", [60, 62])
+@pytest.mark.parametrize("logN", list(range(1, 18)))
+def test_every_candidate_plan(logN, bits):
+    N = 1 << logN
+    seed = 3000 + 100 * bits + logN
+    primes = synth.gen_primes(seed, N, bits, L)
+    psis = oracle.roots(primes, N)
+    a = synth.residue_batch(seed, primes, N, P)
+    b = synth.residue_batch(seed + 1, primes, N, P)
+    # extreme operands in the first vector of b: q - 1 everywhere
+    b[0, 0, :] = np.uint64(primes[0] - 1)
+    want_f = oracle.forward(a, primes, psis, THREADS)
+    want_i = oracle.inverse(a, primes, psis, THREADS)
+    want_m = oracle.polymul(a, b, primes, psis, THREADS)
+    da, db = dev(a), dev(b)
+    checked, refused = [], []
+    for opts in autotune.candidates(N):
+        try:
+            plan = ntt.ntt_plan_create(N, primes, **opts)
+        except ntt.NttError as e:
+            # the fused launch exists only for primes below 2^60; nothing else may be refused
+            assert bits > 60 and opts.get("kernel_path") == ntt.PATH_FUSED, f"{opts}: {e}"
+            refused.append(opts)
+            continue
+        try:
+            assert ntt.ntt_plan_get_roots(plan) == psis
+            d = da.clone()
+            ntt.ntt_forward(plan, d)
+            torch.cuda.synchronize()
+            assert np.array_equal(host(d), want_f), f"N=2^{logN} q<2^{bits} {opts}: forward"
+            ntt.ntt_inverse(plan, d)
+            torch.cuda.synchronize()
+            assert np.array_equal(host(d), a), f"N=2^{logN} q<2^{bits} {opts}: inverse(forward)"
+            d = da.clone()
+            ntt.ntt_inverse(plan, d)
+            torch.cuda.synchronize()
+            assert np.array_equal(host(d), want_i), f"N=2^{logN} q<2^{bits} {opts}: inverse"
+            c = torch.empty_like(da)
+            ntt.ntt_polymul_negacyclic(plan, da, db, c)
+            torch.cuda.synchronize()
+            assert np.array_equal(host(c), want_m), f"N=2^{logN} q<2^{bits} {opts}: product"
+            assert np.array_equal(host(da), a) and np.array_equal(host(db), b), "operands changed"
+            checked.append(opts)
+        finally:
+            plan.destroy()
+    assert checked, "no candidate plan was built"
+    # at 60 bits the sweep must reach every candidate
+    if bits == 60:
+        assert not refused

@@ -579,3 +579,44 @@ def test_batch_mulkey_ot_and_wide_plans(mode):
     finally:
         for p in plans:
             p.destroy()
+
+
+@pytest.mark.parametrize("mode", ["grouped", "graph"])
+def test_config4_full_uneven_batch(mode):
+    """The full uneven workload (256 polys, N from 2^13 to 2^17, L uniform in [4, 60], seed 4)
+    with the plans the benchmark builds for it (the tuner's cached choice per size, else the
+    default): forward NTT of every polynomial in one batch against the oracle, then forward +
+    inverse jobs returning every polynomial unchanged."""
+    b = _bench_module()
+    cfg = b.UNEVEN
+    chain, logNs, Ls = b.uneven_jobs(cfg)
+    Lmax = cfg["L"][1]
+    from paper_2012_01968_amd import autotune
+    plans, src, want = {}, {}, {}
+    try:
+        for k in cfg["logNs"]:
+            k = int(k)
+            polys_k = max(1, -(-int(Ls[logNs == k].sum()) // Lmax))
+            entry = autotune.lookup(1 << k, chain, polys_k)
+            plans[k] = ntt.ntt_plan_create(1 << k, chain, **(entry["opts"] if entry else {}))
+            s = synth.residue_batch(cfg["seed"] + k, chain, 1 << k, 1).reshape(Lmax, 1 << k)
+            src[k] = s
+            want[k] = oracle.forward(s, chain, oracle.roots(chain, 1 << k), THREADS)
+        m = ntt.BATCH_GROUPED if mode == "grouped" else ntt.BATCH_GRAPH
+        for op in (ntt.OP_FORWARD, ntt.OP_FORWARD_INVERSE):
+            bufs, jobs = [], []
+            for k, L in zip(logNs.tolist(), Ls.tolist()):
+                d = dev(src[k][:L])
+                bufs.append(d)
+                jobs.append((plans[k], d, 1, L if L < Lmax else 0, op))
+            batch = ntt.ntt_batch_create(jobs)
+            ntt.ntt_batch_run(batch, m)
+            torch.cuda.synchronize()
+            for i, (d, k, L) in enumerate(zip(bufs, logNs.tolist(), Ls.tolist())):
+                expect = want[k][:L] if op == ntt.OP_FORWARD else src[k][:L]
+                assert np.array_equal(host(d), expect), f"poly {i}: N=2^{k} L={L} op={op}"
+            batch.destroy()
+            del bufs
+    finally:
+        for p in plans.values():
+            p.destroy()
