@@ -175,3 +175,39 @@ def natural_order(x) -> np.ndarray:
 def roots(primes, N: int) -> list[int]:
     """The root convention for every prime: smallest primitive 2N-th root of unity."""
     return [find_psi(int(q), N) for q in primes]
+
+
+def rns_decompose_words(words, primes) -> np.ndarray:
+    """[P][W][N] little-endian 64-bit words of integers -> [P][L][N] residues (Section III-B)."""
+    import synth
+    words = _u64(words)
+    P, W, N = words.shape
+    out = np.empty((P, len(primes), N), dtype=np.uint64)
+    for p in range(P):
+        xs = synth.words_to_ints(words[p])
+        for l, q in enumerate(primes):
+            out[p, l] = [x % int(q) for x in xs]
+    return out
+
+
+def crt_words(primes) -> int:
+    """64-bit words of Q = prod q_l: the width of a reconstructed integer."""
+    Q = 1
+    for q in primes:
+        Q *= int(q)
+    return max(1, (Q.bit_length() + 63) // 64)
+
+
+def crt_reconstruct_words(res, primes) -> np.ndarray:
+    """[P][L][N] residues -> [P][W][N] little-endian words of the integers in [0, Q) they
+    represent (Chinese remainder theorem, one coefficient at a time)."""
+    import synth
+    res = _u64(res)
+    P, L, N = res.shape
+    W = crt_words(primes)
+    out = np.empty((P, W, N), dtype=np.uint64)
+    for p in range(P):
+        cols = [res[p, l].tolist() for l in range(L)]
+        xs = [py.crt_reconstruct([cols[l][j] for l in range(L)], primes) for j in range(N)]
+        out[p] = synth.ints_to_words(xs, W)
+    return out

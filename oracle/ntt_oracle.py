@@ -23,6 +23,10 @@ What each function follows:
   the reading recorded in the design notes).
 * ``negacyclic_schoolbook`` -- the convolution formula of Section III-A,
   c_k = sum_{i<=k} a_i b_{k-i} - sum_{i>k} a_i b_{N+k-i}.
+* ``rns_decompose`` / ``crt_reconstruct`` -- the residue number system of Section III-B:
+  an integer below Q = q_0 q_1 ... q_{L-1} is held as its residues mod each q_l, and the
+  Chinese remainder theorem recovers it as sum_l r_l M_l (M_l^{-1} mod q_l) mod Q with
+  M_l = Q / q_l.
 * ``find_psi`` -- the root convention: the smallest primitive 2N-th root of unity
   mod q (the paper does not say which root; this is the stated reading).
 """
@@ -256,3 +260,24 @@ def negacyclic_schoolbook(a: list[int], b: list[int], q: int) -> list[int]:
 def polymul_ntt(a: list[int], b: list[int], q: int, psi: int) -> list[int]:
     """c = iNTT(NTT(a) * NTT(b)) with both twists merged (Section III-A)."""
     return inverse_gs(pointwise(forward_radix2(a, q, psi), forward_radix2(b, q, psi), q), q, psi)
+
+
+# ------------------------------------------------------------------ residue number system
+
+def rns_decompose(x: int, primes) -> list[int]:
+    """Residues of the integer x modulo each prime (Section III-B's RNS form)."""
+    return [int(x) % int(q) for q in primes]
+
+
+def crt_reconstruct(residues, primes) -> int:
+    """The unique x in [0, Q) with x = r_l mod q_l for every l (Chinese remainder theorem):
+    x = sum_l r_l * M_l * (M_l^{-1} mod q_l) mod Q, M_l = Q / q_l."""
+    Q = 1
+    for q in primes:
+        Q *= int(q)
+    acc = 0
+    for r, q in zip(residues, primes):
+        q = int(q)
+        M = Q // q
+        acc += int(r) * M * pow(M % q, q - 2, q)
+    return acc % Q

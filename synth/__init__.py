@@ -29,6 +29,7 @@ MASK64 = (1 << 64) - 1
 TAG_PRIMES = 0x5052494D  # "PRIM"
 TAG_DATA = 0x44415441    # "DATA"
 TAG_MISC = 0x4D495343    # "MISC"
+TAG_WIDE = 0x57494445    # "WIDE"
 
 
 def mix64(z: int) -> int:
@@ -191,3 +192,63 @@ def uniform_unit(seed: int, tag_a: int, count: int) -> np.ndarray:
     k = key(seed, TAG_MISC, tag_a, 0)
     z = stream_np(k, np.arange(1, count + 1, dtype=np.uint64))
     return (z >> np.uint64(11)).astype(np.float64) * (1.0 / (1 << 53))
+
+
+# ---------------------------------------------------------------- wide integers (inputs)
+
+def words_needed(bound: int) -> int:
+    """64-bit words that hold every integer below ``bound``."""
+    return max(1, ((bound - 1).bit_length() + 63) // 64)
+
+
+def uniform_wide(seed: int, poly: int, bound: int, n: int) -> np.ndarray:
+    """n integers uniform on [0, bound), as a [W][n] uint64 array of little-endian 64-bit
+    words (W = words_needed(bound)).  Attempt a of element j takes word w from counter
+    (a*W + w)*n + j + 1 of the stream key(seed, TAG_WIDE, poly, W), the top word masked to
+    bound's bit length; a draw at or above bound is redrawn (rejection sampling)."""
+    W = words_needed(bound)
+    k = key(seed, TAG_WIDE, poly, W)
+    top_bits = (bound - 1).bit_length() - 64 * (W - 1)
+    top_mask = np.uint64((1 << top_bits) - 1) if top_bits < 64 else np.uint64(0xFFFFFFFFFFFFFFFF)
+    bw = [np.uint64((bound >> (64 * w)) & 0xFFFFFFFFFFFFFFFF) for w in range(W)]
+    idx = np.arange(n, dtype=np.uint64)
+    out = np.empty((W, n), dtype=np.uint64)
+    todo = np.arange(n)
+    attempt = 0
+    while todo.size:
+        for w in range(W):
+            c = (np.uint64(attempt * W + w) * np.uint64(n)) + idx[todo] + np.uint64(1)
+            out[w, todo] = stream_np(k, c)
+        out[W - 1, todo] &= top_mask
+        less = np.zeros(todo.size, dtype=bool)
+        eq = np.ones(todo.size, dtype=bool)
+        for w in range(W - 1, -1, -1):
+            v = out[w, todo]
+            less |= eq & (v < bw[w])
+            eq &= v == bw[w]
+        todo = todo[~less]
+        attempt += 1
+        if attempt > 200:
+            raise RuntimeError("rejection sampling did not converge")
+    return out
+
+
+def words_to_ints(words: np.ndarray) -> list[int]:
+    """The integers held by a [W][n] array of little-endian 64-bit words."""
+    W, n = words.shape
+    out = [0] * n
+    for w in range(W - 1, -1, -1):
+        col = words[w].tolist()
+        out = [(x << 64) | int(c) for x, c in zip(out, col)]
+    return out
+
+
+def ints_to_words(values, W: int) -> np.ndarray:
+    """[W][n] little-endian 64-bit words of non-negative integers below 2^(64 W)."""
+    vals = [int(v) for v in values]
+    out = np.empty((W, len(vals)), dtype=np.uint64)
+    for w in range(W):
+        out[w] = [(v >> (64 * w)) & 0xFFFFFFFFFFFFFFFF for v in vals]
+    if any(v >> (64 * W) for v in vals):
+        raise ValueError("value does not fit in W words")
+    return out

@@ -390,3 +390,90 @@ def test_natural_order_of_the_c_oracle():
     nat = oracle.natural_order(oracle.forward(data, q_list, psis))
     for l, q in enumerate(q_list):
         assert nat[0, l].tolist() == O.forward_natural_definition(data[0, l].tolist(), q, psis[l])
+
+
+# ----------------------------------------------------------------- residue number system (Section III-B)
+
+def _crt_golden():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "crt_examples.txt")
+    out = []
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        kind, name, mods, res, x = [f.strip() for f in line.split("|")]
+        assert kind == "crt"
+        out.append((name, _ints(mods), _ints(res), int(x)))
+    return out
+
+
+def _crt_pins_hold(reconstruct):
+    """Pins of a reconstruction: the hand-derived cases, round trips at full width (45 primes
+    of 60 bits), the ring homomorphism, and the idempotents (e_l maps to the number that is 1
+    mod q_l and 0 mod every other prime)."""
+    for name, mods, res, x in _crt_golden():
+        if reconstruct(res, mods) != x or O.rns_decompose(x, mods) != res:
+            return False
+    primes = synth.gen_primes(2, 1 << 16, 60, 45)
+    Q = 1
+    for q in primes:
+        Q *= q
+    xs = synth.words_to_ints(synth.uniform_wide(11, 0, Q, 40))
+    for x in xs:
+        if reconstruct(O.rns_decompose(x, primes), primes) != x:
+            return False
+    a, b = xs[0], xs[1]
+    ra, rb = O.rns_decompose(a, primes), O.rns_decompose(b, primes)
+    if reconstruct([u * v % q for u, v, q in zip(ra, rb, primes)], primes) != a * b % Q:
+        return False
+    if reconstruct([(u + v) % q for u, v, q in zip(ra, rb, primes)], primes) != (a + b) % Q:
+        return False
+    for l in (0, 17, 44):
+        e = reconstruct([1 if k == l else 0 for k in range(len(primes))], primes)
+        if any(e % q != (1 if k == l else 0) for k, q in enumerate(primes)):
+            return False
+    return True
+
+
+def test_crt_pins():
+    assert _crt_pins_hold(O.crt_reconstruct)
+
+
+def test_crt_pins_reject_planted_mistakes():
+    def prod(ms):
+        Q = 1
+        for q in ms:
+            Q *= q
+        return Q
+
+    def no_inverse(r, ms):
+        Q = prod(ms)
+        return sum(int(x) * (Q // q) for x, q in zip(r, ms)) % Q
+
+    def no_final_mod(r, ms):
+        Q = prod(ms)
+        return sum(int(x) * (Q // q) * pow((Q // q) % q, q - 2, q) for x, q in zip(r, ms))
+
+    def reduced_weight(r, ms):   # M_l mod q_l in place of M_l
+        Q = prod(ms)
+        return sum(int(x) * ((Q // q) % q) * pow((Q // q) % q, q - 2, q) for x, q in zip(r, ms)) % Q
+
+    for bad in (no_inverse, no_final_mod, reduced_weight):
+        assert not _crt_pins_hold(bad), bad.__name__
+
+
+def test_wide_words_and_batch_conversions():
+    """The word packing round-trips, draws stay below the bound, and the batch conversions
+    of the oracle invert each other on [P][W][N] words."""
+    primes = synth.gen_primes(5, 1 << 10, 60, 7)
+    Q = 1
+    for q in primes:
+        Q *= q
+    w = np.stack([synth.uniform_wide(12, p, Q, 64) for p in range(2)])
+    assert w.shape == (2, oracle.crt_words(primes), 64)
+    for p in range(2):
+        xs = synth.words_to_ints(w[p])
+        assert max(xs) < Q and np.array_equal(synth.ints_to_words(xs, w.shape[1]), w[p])
+    res = oracle.rns_decompose_words(w, primes)
+    assert res.shape == (2, 7, 64)
+    assert np.array_equal(oracle.crt_reconstruct_words(res, primes), w)
