@@ -149,6 +149,8 @@ def main() -> int:
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch section")
     ap.add_argument("--no-polymul", action="store_true", help="skip the large-parameter product section")
     ap.add_argument("--no-ablation", action="store_true", help="skip the Table II ablation-ladder section")
+    ap.add_argument("--no-word32", action="store_true", help="skip the 32-bit word section")
+    ap.add_argument("--no-crt", action="store_true", help="skip the RNS <-> integer conversion section")
     ap.add_argument("--profile-polymul", action="store_true",
                     help="counter-collection driver for the product workload: --steps products with one "
                          "twiddle mode (--variant, --log2-n1), then one plain device copy of an operand")
@@ -358,6 +360,8 @@ def main() -> int:
     torch.cuda.empty_cache()
     polymul = None if args.no_polymul else polymul_bench(args)
     ablation = None if args.no_ablation else ablation_bench(args)
+    word32 = None if args.no_word32 else word32_bench(args, r["ms"])
+    crt = None if args.no_crt else crt_bench(args)
     uneven = None if args.no_uneven else uneven_batch_bench(args)
     serving = serve_bench(args) if args.serve_seconds > 0 else None
 
@@ -384,6 +388,8 @@ def main() -> int:
         "plan_create_ms": plan_ms,
         "polymul": polymul,
         "ablation": ablation,
+        "word32": word32,
+        "crt": crt,
         "uneven_batch": uneven,
         "serving": serving,
         "source_hash": src_hash,
@@ -664,6 +670,111 @@ def ablation_bench(args):
         log(f"[ablation 2^{logN} x {L}] " + ", ".join(f"{k}={v}" for k, v in row.items()))
         del bufs, x
         torch.cuda.empty_cache()
+    return out
+
+
+WORD32 = dict(N=1 << 16, L=90, P=2, bits=30, seed=7)
+
+
+def word32_bench(args, headline_ms):
+    """The 32-bit word path at the headline's modulus budget: one ciphertext of 2 polys at
+    N = 2^16 over 90 primes below 2^30 (about the 45 x 60 bits of the 64-bit workload),
+    forward then inverse per step (360 limb-NTTs), over rotating copies larger than the
+    Infinity Cache; checked against the oracle."""
+    import torch
+    import oracle
+    import synth
+    import paper_2012_01968_amd as ntt
+
+    cfg = WORD32
+    N, L, P = cfg["N"], cfg["L"], cfg["P"]
+    primes = synth.gen_primes(cfg["seed"], N, cfg["bits"], L)
+    host = synth.residue_batch(cfg["seed"], primes, N, P)
+    x = torch.from_numpy(host.astype(np.int32)).to("cuda")
+    R = max(2, int(np.ceil(args.rotate_gib * 2**30 / (x.numel() * 4))))
+    bufs = x.unsqueeze(0).repeat(R, 1, 1, 1)
+    plan = ntt.ntt_plan_create(N, primes, word_bits=32)
+    d = x.clone()
+    ntt.ntt_forward_u32(plan, d)
+    torch.cuda.synchronize()
+    want = oracle.forward(host, primes, oracle.roots(primes, N), max(1, min(16, os.cpu_count() or 1)))
+    ok = bool(np.array_equal(d.cpu().numpy().astype(np.uint64), want))
+
+    def step(i):
+        ntt.ntt_forward_u32(plan, bufs[i % R])
+        ntt.ntt_inverse_u32(plan, bufs[i % R])
+
+    ramp(step, args.ramp_ms)
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(args.steps):
+        step(i)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    ok &= bool(torch.equal(bufs[0], x))
+    info = ntt.ntt_plan_get_info(plan)
+    plan.destroy()
+    limb_ntts = 2 * P * L
+    # two passes per direction, 4 B read + 4 B written per coefficient and pass, 8 B per twiddle
+    n1 = 1 << info["log2_n1"] if info["log2_n1"] else 1
+    step_bytes = 2 * (2 * 8 * P * L * N + 8 * L * N) if info["log2_n1"] else 2 * (8 * P * L * N + 8 * L * N)
+    del bufs
+    torch.cuda.empty_cache()
+    out = {"workload": f"one ciphertext, N=2^16, L={L} primes in [2^29,2^30) (seed {cfg['seed']}), {P} polys, "
+                       "forward+inverse", "log2_n1": info["log2_n1"], "n1": n1,
+           "ms_per_step": round(ms, 5), "limb_ntts_per_s": round(limb_ntts / (ms * 1e-3), 1),
+           "modulus_bits": sum(q.bit_length() for q in primes),
+           "step_hbm_frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "speedup_vs_64bit_headline": round(headline_ms / ms, 3) if headline_ms else None,
+           "matches_oracle": ok}
+    log(f"[word32] {ms * 1e3:.1f} us/step ({limb_ntts / ms / 1e3:.3f} M limb-NTTs/s), "
+        f"{headline_ms / ms if headline_ms else float('nan'):.2f}x the 64-bit step, oracle={'ok' if ok else 'MISMATCH'}")
+    return out
+
+
+def crt_bench(args):
+    """RNS <-> integer conversions at the headline shape (N = 2^16, 45 primes of 60 bits,
+    2 polys): integers below Q to residues and back, time per call, with the first 256
+    coefficients of each polynomial checked against the oracle."""
+    import torch
+    import oracle
+    import synth
+    import paper_2012_01968_amd as ntt
+
+    N, L, P = WORKLOAD["N"], WORKLOAD["L"], WORKLOAD["P"]
+    primes = synth.gen_primes(WORKLOAD["seed"], N, WORKLOAD["bits"], L)
+    Q = 1
+    for q in primes:
+        Q *= q
+    plan = ntt.ntt_plan_create(N, primes)
+    W = ntt.ntt_crt_words(plan)
+    words = np.stack([synth.uniform_wide(13, p, Q, N) for p in range(P)])
+    dw = torch.from_numpy(words.view(np.int64)).to("cuda")
+    res = torch.empty((P, L, N), dtype=torch.int64, device="cuda")
+    back = torch.empty_like(dw)
+    out = {"workload": f"{P} polys, N=2^16, integers below Q = product of {L} primes of 60 bits ({W} words)"}
+    for name, fn in (("decompose", lambda: ntt.ntt_rns_decompose(plan, dw, W, res)),
+                     ("reconstruct", lambda: ntt.ntt_crt_reconstruct(plan, res, back))):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name + "_us"] = round(e0.elapsed_time(e1) * 1e3 / 10, 2)
+    k = 256
+    got_res = res.cpu().numpy().view(np.uint64)[:, :, :k]
+    ok = bool(np.array_equal(got_res, oracle.rns_decompose_words(words[:, :, :k], primes)))
+    ok &= bool(np.array_equal(back.cpu().numpy().view(np.uint64), words))
+    out["matches_oracle"] = ok
+    plan.destroy()
+    log(f"[crt] decompose {out['decompose_us']} us, reconstruct {out['reconstruct_us']} us, oracle={'ok' if ok else 'MISMATCH'}")
     return out
 
 

@@ -77,7 +77,8 @@ typedef struct {
     int32_t tune_polys;     /* polynomials per call the plan is tuned for; 0 = 1         */
     int32_t order;          /* NTT_ORDER_*: slot order of the NTT domain (see below)     */
     int32_t log2_radix;     /* NTT_PATH_REGISTER: stages per launch, 2..5; 0 = 4         */
-    int32_t reserved[2];    /* must be zero                                             */
+    int32_t word_bits;      /* residue word: 0 or 64 = uint64_t, 32 = uint32_t (below)   */
+    int32_t reserved;       /* must be zero                                             */
 } ntt_plan_opts;
 
 /* Slot order of the NTT domain (Section III-C).  BITREV (the default) is Algorithm 1's own
@@ -265,6 +266,53 @@ ntt_status ntt_batch_run(ntt_batch_t batch, int32_t mode, void* stream);
 /* Release the batch (its descriptors, private stream and captured graph).  The caller
  * must make sure no run is still in flight.  NULL is accepted. */
 ntt_status ntt_batch_destroy(ntt_batch_t batch);
+
+/* ---------------------------------------------------------------- 32-bit words
+ *
+ * The word-size choice of Section IV taken the other way: a plan created with word_bits = 32
+ * holds residues in uint32_t words, for primes below 2^30 (four times a prime fits a word,
+ * so the lazy butterfly ranges hold), and Shoup products of one high and two low 32x32
+ * multiplies.  The same modulus budget takes twice the limbs of 64-bit words.  Such a plan
+ * takes table twiddles, the split (or single-pass) kernels and bit-reversed order; other
+ * options return NTT_ERR_UNSUPPORTED and primes at or above 2^30 NTT_ERR_PRIME.  Its data
+ * goes through the _u32 calls below ([n_polys][L][N] uint32_t, device, 16-byte aligned),
+ * with the same meaning, order, streams and errors as their 64-bit counterparts; the other
+ * data calls and batches refuse a 32-bit plan (NTT_ERR_ARG / NTT_ERR_UNSUPPORTED), and the
+ * _u32 calls refuse a 64-bit one. */
+ntt_status ntt_forward_u32(ntt_plan_t plan, uint32_t* d_data, uint32_t n_polys, void* stream);
+ntt_status ntt_inverse_u32(ntt_plan_t plan, uint32_t* d_data, uint32_t n_polys, void* stream);
+ntt_status ntt_pointwise_mul_u32(ntt_plan_t plan, const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_c,
+                                 uint32_t n_polys, void* stream);
+ntt_status ntt_polymul_negacyclic_u32(ntt_plan_t plan, const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_c,
+                                      uint32_t n_polys, void* stream);
+
+/* 32 or 64: the plan's residue word; -1 for a NULL or destroyed plan. */
+int32_t ntt_plan_word_bits(ntt_plan_t plan);
+
+/* ---------------------------------------------------------------- RNS <-> integers
+ *
+ * The conversions on either side of the transform (Section III-B): a coefficient of
+ * Z_Q[X]/(X^N+1), Q = q_0 q_1 ... q_{L-1} (the plan's primes), is held in RNS form as its L
+ * residues.  Integers are arrays of little-endian 64-bit words stored word-major:
+ * [n_polys][W][N] uint64_t, word w of coefficient c of polynomial p at (p*W + w)*N + c.
+ * The first call that needs them builds the conversion tables (Q / q_l, their inverses mod
+ * q_l, 2^(64 w) mod q_l, the multiples of Q) and uploads them to the plan's device (a device
+ * allocation).  64-bit plans only. */
+
+/* Words of Q: the width W of a reconstructed integer.  0 for a NULL, destroyed or 32-bit plan
+ * or when the tables cannot be built. */
+uint32_t ntt_crt_words(ntt_plan_t plan);
+
+/* d_res [n_polys][L][N] = the residues of the n_words-word integers in d_words (any values
+ * below 2^(64 n_words), 1 <= n_words <= 64) modulo each prime, canonical. */
+ntt_status ntt_rns_decompose(ntt_plan_t plan, const uint64_t* d_words, uint32_t n_words, uint64_t* d_res,
+                             uint32_t n_polys, void* stream);
+
+/* d_words [n_polys][W][N], W = ntt_crt_words(plan): the unique integer in [0, Q) with the
+ * canonical residues d_res [n_polys][L][N] (Chinese remainder theorem).  L <= 64
+ * (NTT_ERR_UNSUPPORTED above); d_words must not alias d_res. */
+ntt_status ntt_crt_reconstruct(ntt_plan_t plan, const uint64_t* d_res, uint64_t* d_words, uint32_t n_polys,
+                               void* stream);
 
 /* Human-readable name of a status code (static storage). */
 const char* ntt_status_string(ntt_status s);

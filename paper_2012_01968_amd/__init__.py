@@ -22,7 +22,9 @@ __all__ = [
     "Batch", "ntt_batch_create", "ntt_batch_run", "ntt_batch_destroy", "ntt_batch_assign", "OP_FORWARD", "OP_INVERSE",
     "OP_FORWARD_INVERSE", "OP_MULKEY", "BATCH_PLAIN", "BATCH_GROUPED", "BATCH_GRAPH",
     "library_path", "TWIDDLE_AUTO", "TWIDDLE_TABLE", "TWIDDLE_OT", "PATH_AUTO", "PATH_SPLIT", "PATH_FUSED",
-    "PATH_RADIX2", "PATH_REGISTER", "ntt_plan_log2_radix",
+    "PATH_RADIX2", "PATH_REGISTER", "ntt_plan_log2_radix", "ntt_forward_u32", "ntt_inverse_u32",
+    "ntt_pointwise_mul_u32", "ntt_polymul_negacyclic_u32", "ntt_plan_word_bits", "ntt_crt_words",
+    "ntt_rns_decompose", "ntt_crt_reconstruct",
 ]
 
 TWIDDLE_AUTO, TWIDDLE_TABLE, TWIDDLE_OT = 0, 1, 2
@@ -72,7 +74,7 @@ class _Opts(ctypes.Structure):
                 ("ot_log2_base", ctypes.c_int32), ("log2_n1", ctypes.c_int32),
                 ("kernel_path", ctypes.c_int32), ("use_autotune", ctypes.c_int32),
                 ("tune_polys", ctypes.c_int32), ("order", ctypes.c_int32), ("log2_radix", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("word_bits", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p
@@ -106,6 +108,20 @@ _lib.ntt_plan_log2_radix.restype = ctypes.c_int32
 _lib.ntt_plan_tuned.restype = ctypes.c_int32
 _lib.ntt_pointwise_mul.argtypes = [_vp, _vp, _vp, _vp, _u32, _vp]
 _lib.ntt_polymul_negacyclic.argtypes = [_vp, _vp, _vp, _vp, _u32, _vp]
+for _f in ("ntt_forward_u32", "ntt_inverse_u32"):
+    getattr(_lib, _f).argtypes = [_vp, _vp, _u32, _vp]
+    getattr(_lib, _f).restype = ctypes.c_int
+for _f in ("ntt_pointwise_mul_u32", "ntt_polymul_negacyclic_u32"):
+    getattr(_lib, _f).argtypes = [_vp, _vp, _vp, _vp, _u32, _vp]
+    getattr(_lib, _f).restype = ctypes.c_int
+_lib.ntt_plan_word_bits.argtypes = [_vp]
+_lib.ntt_plan_word_bits.restype = ctypes.c_int32
+_lib.ntt_crt_words.argtypes = [_vp]
+_lib.ntt_crt_words.restype = _u32
+_lib.ntt_rns_decompose.argtypes = [_vp, _vp, _u32, _vp, _u32, _vp]
+_lib.ntt_rns_decompose.restype = ctypes.c_int
+_lib.ntt_crt_reconstruct.argtypes = [_vp, _vp, _vp, _u32, _vp]
+_lib.ntt_crt_reconstruct.restype = ctypes.c_int
 _lib.ntt_batch_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_Job), _u32]
 _lib.ntt_batch_run.argtypes = [_vp, ctypes.c_int32, _vp]
 _lib.ntt_batch_assign.argtypes = [_vp, ctypes.POINTER(_Job), _u32, _vp]
@@ -156,9 +172,9 @@ class Plan:
             pass
 
 
-def _addr(buf, need: int | None = None, what: str = "buffer") -> int:
+def _addr(buf, need: int | None = None, what: str = "buffer", esize: int = 8) -> int:
     """Device address of `buf` for the C ABI.  A raw integer is passed through as given (the
-    caller vouches for it).  A tensor must live on the GPU, hold 8-byte integers, be
+    caller vouches for it).  A tensor must live on the GPU, hold integers of `esize` bytes, be
     contiguous and have at least `need` elements: anything else would reach the kernels as a
     pointer to memory they cannot address or to too few elements."""
     if buf is None:
@@ -167,8 +183,8 @@ def _addr(buf, need: int | None = None, what: str = "buffer") -> int:
         return buf
     if not getattr(buf, "is_cuda", False):
         raise ValueError(f"{what} must be a tensor in GPU memory")
-    if buf.element_size() != 8 or buf.dtype.is_floating_point or buf.dtype.is_complex:
-        raise ValueError(f"{what} must hold 64-bit integers (int64 or uint64), not {buf.dtype}")
+    if buf.element_size() != esize or buf.dtype.is_floating_point or buf.dtype.is_complex:
+        raise ValueError(f"{what} must hold {8 * esize}-bit integers, not {buf.dtype}")
     if not buf.is_contiguous():
         raise ValueError(f"{what} must be contiguous")
     if need is not None and buf.numel() < need:
@@ -199,20 +215,20 @@ def _polys(plan: Plan, buf, n_polys) -> int:
     return numel // per
 
 
-def _batch_addrs(plan: Plan, bufs, names, n_polys):
+def _batch_addrs(plan: Plan, bufs, names, n_polys, esize: int = 8):
     """n_polys and the addresses of same-shaped [n_polys][L][N] operands."""
     n = _polys(plan, bufs[0], n_polys)
     need = n * plan.L * plan.N
-    return n, [_addr(b, need, w) for b, w in zip(bufs, names)]
+    return n, [_addr(b, need, w, esize) for b, w in zip(bufs, names)]
 
 
 def ntt_plan_create(N: int, primes, *, twiddle_mode: int = 0, ot_stages: int = 0, ot_log2_base: int = 0,
                     log2_n1: int = 0, kernel_path: int = 0, use_autotune: int = 0, tune_polys: int = 0,
-                    order: int = 0, log2_radix: int = 0) -> Plan:
+                    order: int = 0, log2_radix: int = 0, word_bits: int = 0) -> Plan:
     primes = [int(q) for q in primes]
     arr = (ctypes.c_uint64 * len(primes))(*primes)
     opts = _Opts(twiddle_mode, ot_stages, ot_log2_base, log2_n1, kernel_path, int(use_autotune), int(tune_polys),
-                 int(order), int(log2_radix))
+                 int(order), int(log2_radix), int(word_bits))
     h = _vp()
     _check(_lib.ntt_plan_create(ctypes.byref(h), N, arr, len(primes), ctypes.byref(opts)), "ntt_plan_create")
     return Plan(h.value, N, len(primes))
@@ -293,6 +309,68 @@ def ntt_pointwise_mul(plan: Plan, a, b, c, n_polys: int | None = None, stream=No
 def ntt_polymul_negacyclic(plan: Plan, a, b, c, n_polys: int | None = None, stream=None) -> None:
     n, (pa, pb, pc) = _batch_addrs(plan, [a, b, c], ["a", "b", "c"], n_polys)
     _check(_lib.ntt_polymul_negacyclic(plan.handle, pa, pb, pc, n, _stream(stream)), "ntt_polymul_negacyclic")
+
+
+# ---------------------------------------------------------------- 32-bit words
+# Plans created with word_bits=32 (primes below 2^30) take [n_polys][L][N] tensors of 4-byte
+# integers (int32 or uint32) through these calls.
+
+def ntt_forward_u32(plan: Plan, data, n_polys: int | None = None, stream=None) -> None:
+    n, (d,) = _batch_addrs(plan, [data], ["data"], n_polys, 4)
+    _check(_lib.ntt_forward_u32(plan.handle, d, n, _stream(stream)), "ntt_forward_u32")
+
+
+def ntt_inverse_u32(plan: Plan, data, n_polys: int | None = None, stream=None) -> None:
+    n, (d,) = _batch_addrs(plan, [data], ["data"], n_polys, 4)
+    _check(_lib.ntt_inverse_u32(plan.handle, d, n, _stream(stream)), "ntt_inverse_u32")
+
+
+def ntt_pointwise_mul_u32(plan: Plan, a, b, c, n_polys: int | None = None, stream=None) -> None:
+    n, (pa, pb, pc) = _batch_addrs(plan, [a, b, c], ["a", "b", "c"], n_polys, 4)
+    _check(_lib.ntt_pointwise_mul_u32(plan.handle, pa, pb, pc, n, _stream(stream)), "ntt_pointwise_mul_u32")
+
+
+def ntt_polymul_negacyclic_u32(plan: Plan, a, b, c, n_polys: int | None = None, stream=None) -> None:
+    n, (pa, pb, pc) = _batch_addrs(plan, [a, b, c], ["a", "b", "c"], n_polys, 4)
+    _check(_lib.ntt_polymul_negacyclic_u32(plan.handle, pa, pb, pc, n, _stream(stream)),
+           "ntt_polymul_negacyclic_u32")
+
+
+def ntt_plan_word_bits(plan: Plan) -> int:
+    r = int(_lib.ntt_plan_word_bits(plan.handle))
+    if r < 0:
+        raise NttError(-1, "ntt_plan_word_bits")
+    return r
+
+
+# ---------------------------------------------------------------- RNS <-> integers
+# Integers are [n_polys][W][N] int64/uint64 tensors of little-endian 64-bit words.
+
+def ntt_crt_words(plan: Plan) -> int:
+    """W: the 64-bit words of Q, the width of a reconstructed coefficient."""
+    w = int(_lib.ntt_crt_words(plan.handle))
+    if w == 0:
+        raise NttError(-1, "ntt_crt_words")
+    return w
+
+
+def ntt_rns_decompose(plan: Plan, words, n_words: int, res, n_polys: int | None = None, stream=None) -> None:
+    if n_polys is None:
+        if isinstance(words, int):
+            raise ValueError("n_polys is required when a buffer is given as a raw address")
+        n_polys = words.numel() // (int(n_words) * plan.N)
+    n_polys = int(n_polys)
+    if n_polys < 1:
+        raise ValueError("n_polys must be at least 1")
+    pw = _addr(words, n_polys * int(n_words) * plan.N, "words")
+    pr = _addr(res, n_polys * plan.L * plan.N, "res")
+    _check(_lib.ntt_rns_decompose(plan.handle, pw, int(n_words), pr, n_polys, _stream(stream)), "ntt_rns_decompose")
+
+
+def ntt_crt_reconstruct(plan: Plan, res, words, n_polys: int | None = None, stream=None) -> None:
+    n, (pr,) = _batch_addrs(plan, [res], ["res"], n_polys)
+    pw = _addr(words, n * ntt_crt_words(plan) * plan.N, "words")
+    _check(_lib.ntt_crt_reconstruct(plan.handle, pr, pw, n, _stream(stream)), "ntt_crt_reconstruct")
 
 
 class Batch:

@@ -18,7 +18,8 @@ BUILD = os.environ.get("NTT_BUILD_DIR") or os.path.join(ROOT, "_build", "ntt")
 LIB = os.environ.get("NTT_BUILD_OUT") or os.path.join(HERE, "libntt_mi355x.so")
 SOURCES = ["kernels_fwd_fast.hip", "kernels_inv_fast.hip", "kernels_fwd_wide.hip", "kernels_inv_wide.hip",
            "kernels_mul_fast.hip", "kernels_mul_wide.hip",
-           "fused_fwd.hip", "fused_inv.hip", "kernels.hip", "permute.hip", "stages.hip", "capi.cpp"]
+           "fused_fwd.hip", "fused_inv.hip", "kernels.hip", "permute.hip", "stages.hip", "kernels32.hip", "crt.hip",
+           "capi.cpp"]
 ARCH = os.environ.get("NTT_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -32,7 +33,7 @@ FLAGS = [
 
 # Host-only sources: they decide which launches happen but hold no device code, so a change
 # there leaves every kernel's measured time (and the counters taken of it) valid.
-HOST_ONLY_SOURCES = ("capi.cpp", "plan_math.hpp", "plan_life.hpp", "tune_file.hpp")
+HOST_ONLY_SOURCES = ("capi.cpp", "plan_math.hpp", "plan_life.hpp", "tune_file.hpp", "crt_math.hpp")
 
 
 def source_hash() -> str:

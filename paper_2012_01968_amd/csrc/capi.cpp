@@ -17,6 +17,7 @@
 #include <thread>
 #include <vector>
 
+#include "crt_math.hpp"
 #include "kernels.hpp"
 #include "passes.hpp"
 #include "plan_life.hpp"
@@ -80,6 +81,7 @@ struct ntt_plan_s {
   int32_t kernel_path = NTT_PATH_SPLIT;   // SPLIT or FUSED after creation
   int32_t order = NTT_ORDER_BITREV;       // NTT-domain slot order seen by the caller
   int32_t log2_radix = 0;                 // RADIX2 / REGISTER paths: stages per launch
+  int32_t word_bits = 64;                 // residue word: 64 (uint64_t) or 32 (uint32_t, q < 2^30)
   uint32_t fused_lag = 4;                 // vectors an XCD queue runs pass 1 ahead of pass 2
   uint32_t fused_grid = 1024;             // persistent workgroups (4 per CU)
   uint32_t* d_ctr = nullptr;              // fused-launch counters: 16 + kMaxFusedVectors words
@@ -103,6 +105,23 @@ struct ntt_plan_s {
   Tw* d_scale = nullptr;
   uint64_t* d_mu = nullptr;
   uint32_t* d_bits = nullptr;
+  // 32-bit plans: Tw32 {w, floor(w 2^32 / q)} tables, {1/N, Psi_inv[1]/N}, primes, floor(2^64 / q)
+  void* d_tw32_fwd = nullptr;
+  void* d_tw32_inv = nullptr;
+  void* d_scale32 = nullptr;
+  uint32_t* d_q32 = nullptr;
+  uint64_t* d_mu64 = nullptr;
+
+  // RNS <-> integer conversion tables (crt_math.hpp), built and uploaded on first use
+  struct Crt {
+    std::mutex mu;
+    bool ready = false;
+    uint32_t W = 0;                 // words of Q
+    Tw* pow2 = nullptr;             // [L][kCrtMaxInWords]
+    Tw* inv = nullptr;              // [L]
+    uint64_t* M = nullptr;          // [L][W]
+    uint64_t* kQ = nullptr;         // [L + 1][W + 1]
+  } crt;
 
   // References: the creator's and one per batch that names the plan (plan_life.hpp).
   nttl::RefCount rc;
@@ -144,7 +163,8 @@ struct ntt_plan_s {
       (void)hipEventDestroy(fused_ev);
     }
     void* ptrs[] = {d_q, d_mc, d_tw_fwd, d_tw_inv, d_ot_lo_fwd, d_ot_hi_fwd, d_ot_lo_inv, d_ot_hi_inv,
-                    d_scale, d_mu, d_bits, d_ctr};
+                    d_scale, d_mu, d_bits, d_ctr, d_tw32_fwd, d_tw32_inv, d_scale32, d_q32, d_mu64,
+                    crt.pow2, crt.inv, crt.M, crt.kQ};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
   }
@@ -237,14 +257,17 @@ static ntt_status build_plan(ntt_plan_s* p, uint32_t N, const uint64_t* primes, 
 
   ntt_plan_opts o{};
   if (opts) o = *opts;
-  for (int32_t r : o.reserved)
-    if (r != 0) return fail(NTT_ERR_ARG, "reserved option fields must be zero");
+  if (o.reserved != 0) return fail(NTT_ERR_ARG, "the reserved option field must be zero");
   const bool stage_path = o.kernel_path == NTT_PATH_RADIX2 || o.kernel_path == NTT_PATH_REGISTER;
   if (o.use_autotune < 0 || o.use_autotune > 1 || o.tune_polys < 0)
     return fail(NTT_ERR_ARG, "use_autotune must be 0 or 1 and tune_polys non-negative");
   if (o.order != NTT_ORDER_BITREV && o.order != NTT_ORDER_NATURAL)
     return fail(NTT_ERR_ARG, "order must be NTT_ORDER_BITREV or NTT_ORDER_NATURAL");
   p->order = o.order;
+  if (o.word_bits != 0 && o.word_bits != 32 && o.word_bits != 64)
+    return fail(NTT_ERR_ARG, "word_bits must be 0, 32 or 64");
+  p->word_bits = o.word_bits == 32 ? 32 : 64;
+  const bool w32 = p->word_bits == 32;
   if (o.use_autotune) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return fail(NTT_ERR_HIP, "hipGetDevice failed");
@@ -265,7 +288,14 @@ static ntt_status build_plan(ntt_plan_s* p, uint32_t N, const uint64_t* primes, 
   if (mode == NTT_TWIDDLE_OT && p->ot_log2_base >= p->logN)
     return fail(NTT_ERR_UNSUPPORTED, "OT needs a digit base below N");
 
-  if (stage_path) {
+  if (w32) {
+    // 32-bit words: table twiddles, one or two passes, Algorithm 1's order
+    if (mode == NTT_TWIDDLE_OT || stage_path || o.kernel_path == NTT_PATH_FUSED || o.order != NTT_ORDER_BITREV)
+      return fail(NTT_ERR_UNSUPPORTED, "32-bit plans take table twiddles, the split path and bit-reversed order");
+    p->logN1 = o.log2_n1 == 0 ? (p->logN <= 12 ? 0 : p->logN / 2) : (o.log2_n1 < 0 ? 0 : (uint32_t)o.log2_n1);
+    if (!nttk::shape32_supported(p->logN, p->logN1))
+      return fail(NTT_ERR_UNSUPPORTED, "no 32-bit kernels for this (N, N1) combination");
+  } else if (stage_path) {
     // the ablation paths: table twiddles only, no column/row split
     if (mode == NTT_TWIDDLE_OT) return fail(NTT_ERR_UNSUPPORTED, "the radix-2 and register paths take table twiddles");
     if (o.log2_n1) return fail(NTT_ERR_ARG, "log2_n1 does not apply to the radix-2 and register paths");
@@ -296,6 +326,8 @@ static ntt_status build_plan(ntt_plan_s* p, uint32_t N, const uint64_t* primes, 
   for (uint32_t l = 0; l < L; ++l) {
     const uint64_t q = p->primes[l];
     if (q <= 2 || q >= (1ull << 62)) return fail(NTT_ERR_PRIME, "prime " + std::to_string(q) + " not in (2, 2^62)");
+    if (w32 && q >= (1ull << 30))
+      return fail(NTT_ERR_PRIME, "prime " + std::to_string(q) + ": 32-bit words need primes below 2^30");
     if ((q - 1) % (2ull * N)) return fail(NTT_ERR_PRIME, "prime " + std::to_string(q) + " is not 1 mod 2N");
     if (!nttp::is_prime(q)) return fail(NTT_ERR_PRIME, std::to_string(q) + " is not prime");
   }
@@ -307,7 +339,7 @@ static ntt_status build_plan(ntt_plan_s* p, uint32_t N, const uint64_t* primes, 
       return fail(NTT_ERR_UNSUPPORTED, "the fused path needs primes below 2^60 and a built N1 x N2 shape");
     // AUTO takes the split path: on gfx950 the pass-1 output of a split launch already round-trips
     // through the Infinity Cache, and the fused queue measured slower (see the design notes).
-    p->kernel_path = stage_path ? o.kernel_path
+    p->kernel_path = (stage_path || w32) ? (w32 ? NTT_PATH_SPLIT : o.kernel_path)
                                 : (o.kernel_path == NTT_PATH_FUSED && can_fuse) ? NTT_PATH_FUSED : NTT_PATH_SPLIT;
     if (const char* e = std::getenv("NTT_FUSED_LAG")) p->fused_lag = (uint32_t)std::max(1, std::atoi(e));
     if (const char* e = std::getenv("NTT_FUSED_GRID")) p->fused_grid = (uint32_t)std::max(1, std::atoi(e));
@@ -323,6 +355,11 @@ static ntt_status build_plan(ntt_plan_s* p, uint32_t N, const uint64_t* primes, 
   std::vector<uint64_t> mu(L), psis(L);
   std::vector<uint32_t> bits(L);
   std::vector<int> bad(L, 0);
+  // 32-bit tables: {w, floor(w 2^32 / q)} per entry, packed as one uint64 (w in the low half)
+  std::vector<uint64_t> tw32_f(w32 ? L * NN : 0), tw32_i(w32 ? L * NN : 0), scale32(w32 ? 2 * (size_t)L : 0),
+      mu64(w32 ? L : 0);
+  std::vector<uint32_t> q32(w32 ? L : 0);
+  auto pack32 = [](uint64_t w, uint64_t q) { return w | ((uint64_t)(((nttp::u128)w << 32) / q) << 32); };
 
   auto work = [&](uint32_t l0, uint32_t l1) {
     std::vector<uint64_t> pw(NN), pwi(NN);
@@ -364,6 +401,16 @@ static ntt_status build_plan(ntt_plan_s* p, uint32_t N, const uint64_t* primes, 
       while (s < 64 && (q >> s)) ++s;
       bits[l] = s;
       mu[l] = (uint64_t)(((nttp::u128)1 << (2 * s)) / q);
+      if (w32) {
+        for (size_t i = 0; i < NN; ++i) {
+          tw32_f[l * NN + i] = pack32(tf[i].w, q);
+          tw32_i[l * NN + i] = pack32(ti[i].w, q);
+        }
+        scale32[2 * l] = pack32(n_inv, q);
+        scale32[2 * l + 1] = pack32(w1n, q);
+        q32[l] = (uint32_t)q;
+        mu64[l] = (uint64_t)((((nttp::u128)1) << 64) / q);
+      }
     }
   };
   const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
@@ -393,8 +440,22 @@ static ntt_status build_plan(ntt_plan_s* p, uint32_t N, const uint64_t* primes, 
     c[7] = nttk::quot_estimate_consts(q);
   }
 
+  if (w32) {   // a 32-bit plan keeps only its 32-bit tables on the device
+    for (auto* v : {&tw_fwd, &tw_inv, &ot_lo_f, &ot_hi_f, &ot_lo_i, &ot_hi_i, &scale}) std::vector<Tw>().swap(*v);
+  }
   if (hipGetDevice(&p->device) != hipSuccess) return fail(NTT_ERR_HIP, "hipGetDevice failed");
   hipError_t e;
+  {
+    uint64_t* f = nullptr;
+    uint64_t* i = nullptr;
+    uint64_t* sc = nullptr;
+    if ((e = upload(&f, tw32_f)) != hipSuccess || (p->d_tw32_fwd = f, (e = upload(&i, tw32_i)) != hipSuccess) ||
+        (p->d_tw32_inv = i, (e = upload(&sc, scale32)) != hipSuccess) ||
+        (p->d_scale32 = sc, (e = upload(&p->d_q32, q32)) != hipSuccess) || (e = upload(&p->d_mu64, mu64)) != hipSuccess) {
+      if (e == hipErrorOutOfMemory) return fail(NTT_ERR_NOMEM, "device allocation of plan tables failed");
+      return hip_fail(e, "uploading plan tables");
+    }
+  }
   if ((e = upload(&p->d_q, p->primes)) != hipSuccess || (e = upload(&p->d_mc, mod_consts)) != hipSuccess ||
       (e = upload(&p->d_tw_fwd, tw_fwd)) != hipSuccess ||
       (e = upload(&p->d_tw_inv, tw_inv)) != hipSuccess || (e = upload(&p->d_ot_lo_fwd, ot_lo_f)) != hipSuccess ||
@@ -477,8 +538,17 @@ static ntt_status check_plan(ntt_plan_t plan) {
   return NTT_OK;
 }
 
+static ntt_status check_data_words(ntt_plan_t plan, const void* ptr, uint32_t n_polys, int word_bits);
+
 static ntt_status check_data(ntt_plan_t plan, const void* ptr, uint32_t n_polys) {
+  return check_data_words(plan, ptr, n_polys, 64);
+}
+
+static ntt_status check_data_words(ntt_plan_t plan, const void* ptr, uint32_t n_polys, int word_bits) {
   if (ntt_status s = check_plan(plan)) return s;
+  if (plan->word_bits != word_bits)
+    return fail(NTT_ERR_ARG, plan->word_bits == 32 ? "the plan holds 32-bit words: use the _u32 entry points"
+                                                   : "the plan holds 64-bit words: use the uint64_t entry points");
   if (!ptr) return fail(NTT_ERR_ARG, "data pointer is NULL");
   if (reinterpret_cast<uintptr_t>(ptr) & 15) return fail(NTT_ERR_ARG, "data pointer must be 16-byte aligned");
   if (n_polys == 0) return fail(NTT_ERR_ARG, "n_polys must be at least 1");
@@ -661,6 +731,8 @@ static ntt_status plan_batch(ntt_batch_s* b, const ntt_job* jobs, uint32_t n_job
     if (!job.plan || !job.d_data) return fail(NTT_ERR_ARG, "job " + std::to_string(j) + ": NULL plan or data");
     if (job.plan->rc.owner_gone.load(std::memory_order_relaxed))
       return fail(NTT_ERR_ARG, "job " + std::to_string(j) + ": plan was destroyed");
+    if (job.plan->word_bits != 64)
+      return fail(NTT_ERR_UNSUPPORTED, "job " + std::to_string(j) + ": batches take 64-bit plans");
     if (reinterpret_cast<uintptr_t>(job.d_data) & 15) return fail(NTT_ERR_ARG, "job data must be 16-byte aligned");
     if (job.n_polys == 0 || job.n_limbs > job.plan->L || job.reserved)
       return fail(NTT_ERR_ARG, "job " + std::to_string(j) + ": bad n_polys, n_limbs or reserved field");
@@ -1090,6 +1162,196 @@ ntt_status ntt_batch_destroy(ntt_batch_t b) {
     return NTT_OK;
   } catch (...) {
     return fail(NTT_ERR_ARG, "unexpected failure in ntt_batch_destroy");
+  }
+}
+
+// ---------------------------------------------------------------- 32-bit words
+
+ntt_status ntt_forward_u32(ntt_plan_t plan, uint32_t* d_data, uint32_t n_polys, void* stream) {
+  try {
+    if (ntt_status s = check_data_words(plan, d_data, n_polys, 32)) return s;
+    DeviceGuard g(plan->device);
+    if (!g.ok) return fail(NTT_ERR_HIP, "cannot select the plan's device");
+    const hipError_t e = nttk::launch_transform32(d_data, plan->d_tw32_fwd, plan->d_scale32, plan->d_q32,
+                                                  (uint64_t)n_polys * plan->L, plan->L, plan->logN, plan->logN1, false,
+                                                  static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? NTT_OK : hip_fail(e, "ntt_forward_u32 launch");
+  } catch (...) {
+    return fail(NTT_ERR_ARG, "unexpected failure in ntt_forward_u32");
+  }
+}
+
+ntt_status ntt_inverse_u32(ntt_plan_t plan, uint32_t* d_data, uint32_t n_polys, void* stream) {
+  try {
+    if (ntt_status s = check_data_words(plan, d_data, n_polys, 32)) return s;
+    DeviceGuard g(plan->device);
+    if (!g.ok) return fail(NTT_ERR_HIP, "cannot select the plan's device");
+    const hipError_t e = nttk::launch_transform32(d_data, plan->d_tw32_inv, plan->d_scale32, plan->d_q32,
+                                                  (uint64_t)n_polys * plan->L, plan->L, plan->logN, plan->logN1, true,
+                                                  static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? NTT_OK : hip_fail(e, "ntt_inverse_u32 launch");
+  } catch (...) {
+    return fail(NTT_ERR_ARG, "unexpected failure in ntt_inverse_u32");
+  }
+}
+
+ntt_status ntt_pointwise_mul_u32(ntt_plan_t plan, const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_c,
+                                 uint32_t n_polys, void* stream) {
+  try {
+    ntt_status s;
+    if ((s = check_data_words(plan, d_a, n_polys, 32)) || (s = check_data_words(plan, d_b, n_polys, 32)) ||
+        (s = check_data_words(plan, d_c, n_polys, 32)))
+      return s;
+    DeviceGuard g(plan->device);
+    if (!g.ok) return fail(NTT_ERR_HIP, "cannot select the plan's device");
+    const hipError_t e = nttk::launch_pointwise32(d_a, d_b, d_c, plan->d_q32, plan->d_mu64,
+                                                  (uint64_t)n_polys * plan->L * plan->N, plan->logN, plan->L,
+                                                  static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? NTT_OK : hip_fail(e, "ntt_pointwise_mul_u32 launch");
+  } catch (...) {
+    return fail(NTT_ERR_ARG, "unexpected failure in ntt_pointwise_mul_u32");
+  }
+}
+
+ntt_status ntt_polymul_negacyclic_u32(ntt_plan_t plan, const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_c,
+                                      uint32_t n_polys, void* stream) {
+  try {
+    ntt_status s;
+    if ((s = check_data_words(plan, d_a, n_polys, 32)) || (s = check_data_words(plan, d_b, n_polys, 32)) ||
+        (s = check_data_words(plan, d_c, n_polys, 32)))
+      return s;
+    if (d_c == d_b) return fail(NTT_ERR_ARG, "d_c must not alias d_b");
+    DeviceGuard g(plan->device);
+    if (!g.ok) return fail(NTT_ERR_HIP, "cannot select the plan's device");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t bytes = (size_t)n_polys * plan->L * plan->N * sizeof(uint32_t);
+    ntt_plan_s::StreamScratch* sc = plan->scratch_for(st);
+    std::lock_guard<std::mutex> lk(sc->mu);
+    hipError_t e;
+    if (!sc->ev && (e = hipEventCreateWithFlags(&sc->ev, hipEventDisableTiming)) != hipSuccess) {
+      sc->ev = nullptr;
+      return hip_fail(e, "hipEventCreate");
+    }
+    if (sc->bytes < bytes) {
+      if (sc->pending && (e = hipEventSynchronize(sc->ev)) != hipSuccess) return hip_fail(e, "waiting for scratch");
+      if (sc->buf) (void)hipFree(sc->buf);
+      sc->buf = nullptr;
+      sc->bytes = 0;
+      sc->pending = false;
+      if ((e = hipMalloc(reinterpret_cast<void**>(&sc->buf), bytes)) != hipSuccess)
+        return e == hipErrorOutOfMemory ? fail(NTT_ERR_NOMEM, "scratch allocation failed")
+                                        : hip_fail(e, "scratch allocation");
+      sc->bytes = bytes;
+    }
+    uint32_t* tmp = reinterpret_cast<uint32_t*>(sc->buf);
+    const uint64_t n_vec = (uint64_t)n_polys * plan->L;
+    if ((d_c != d_a && (e = hipMemcpyAsync(d_c, d_a, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) ||
+        (e = hipMemcpyAsync(tmp, d_b, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess ||
+        (e = nttk::launch_transform32(d_c, plan->d_tw32_fwd, plan->d_scale32, plan->d_q32, n_vec, plan->L, plan->logN,
+                                      plan->logN1, false, st)) != hipSuccess ||
+        (e = nttk::launch_transform32(tmp, plan->d_tw32_fwd, plan->d_scale32, plan->d_q32, n_vec, plan->L, plan->logN,
+                                      plan->logN1, false, st)) != hipSuccess ||
+        (e = nttk::launch_pointwise32(d_c, tmp, d_c, plan->d_q32, plan->d_mu64, n_vec * plan->N, plan->logN, plan->L,
+                                      st)) != hipSuccess ||
+        (e = nttk::launch_transform32(d_c, plan->d_tw32_inv, plan->d_scale32, plan->d_q32, n_vec, plan->L, plan->logN,
+                                      plan->logN1, true, st)) != hipSuccess)
+      return hip_fail(e, "ntt_polymul_negacyclic_u32 launch");
+    if ((e = hipEventRecord(sc->ev, st)) != hipSuccess) return hip_fail(e, "recording scratch event");
+    sc->pending = true;
+    return NTT_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(NTT_ERR_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(NTT_ERR_ARG, "unexpected failure in ntt_polymul_negacyclic_u32");
+  }
+}
+
+int32_t ntt_plan_word_bits(ntt_plan_t plan) {
+  if (check_plan(plan) != NTT_OK) return -1;
+  return plan->word_bits;
+}
+
+// ---------------------------------------------------------------- RNS <-> integers
+
+static constexpr uint32_t kCrtMaxLimbs = 64;   // reconstruction keeps L words per lane in LDS (32 KB)
+
+// Build the conversion tables of a 64-bit plan and upload them (once).
+static ntt_status crt_prepare(ntt_plan_t plan) {
+  std::lock_guard<std::mutex> lk(plan->crt.mu);
+  if (plan->crt.ready) return NTT_OK;
+  const nttc::CrtTables t = nttc::crt_tables(plan->primes);
+  std::vector<Tw> pow2(t.pow2.size()), inv(t.L);
+  for (uint32_t l = 0; l < t.L; ++l) {
+    const uint64_t q = plan->primes[l];
+    for (uint32_t w = 0; w < nttc::kCrtMaxInWords; ++w) {
+      const uint64_t c = t.pow2[(size_t)l * nttc::kCrtMaxInWords + w];
+      pow2[(size_t)l * nttc::kCrtMaxInWords + w] = Tw{c, nttp::shoup_companion(c, q)};
+    }
+    inv[l] = Tw{t.inv[l], nttp::shoup_companion(t.inv[l], q)};
+  }
+  DeviceGuard g(plan->device);
+  if (!g.ok) return fail(NTT_ERR_HIP, "cannot select the plan's device");
+  hipError_t e;
+  if ((e = upload(&plan->crt.pow2, pow2)) != hipSuccess || (e = upload(&plan->crt.inv, inv)) != hipSuccess ||
+      (e = upload(&plan->crt.M, t.M)) != hipSuccess || (e = upload(&plan->crt.kQ, t.kQ)) != hipSuccess) {
+    if (e == hipErrorOutOfMemory) return fail(NTT_ERR_NOMEM, "device allocation of conversion tables failed");
+    return hip_fail(e, "uploading conversion tables");
+  }
+  plan->crt.W = t.W;
+  plan->crt.ready = true;
+  return NTT_OK;
+}
+
+uint32_t ntt_crt_words(ntt_plan_t plan) {
+  try {
+    if (check_plan(plan) != NTT_OK || plan->word_bits != 64) return 0;
+    if (crt_prepare(plan) != NTT_OK) return 0;
+    return plan->crt.W;
+  } catch (...) {
+    return 0;
+  }
+}
+
+ntt_status ntt_rns_decompose(ntt_plan_t plan, const uint64_t* d_words, uint32_t n_words, uint64_t* d_res,
+                             uint32_t n_polys, void* stream) {
+  try {
+    ntt_status s;
+    if ((s = check_data(plan, d_words, n_polys)) || (s = check_data(plan, d_res, n_polys))) return s;
+    if (n_words == 0 || n_words > nttc::kCrtMaxInWords)
+      return fail(NTT_ERR_ARG, "n_words must be 1.." + std::to_string(nttc::kCrtMaxInWords));
+    if ((s = crt_prepare(plan))) return s;
+    DeviceGuard g(plan->device);
+    if (!g.ok) return fail(NTT_ERR_HIP, "cannot select the plan's device");
+    const hipError_t e = nttk::launch_rns_decompose(d_words, n_words, d_res, n_polys, plan->logN, plan->L,
+                                                    plan->crt.pow2, nttc::kCrtMaxInWords, plan->d_q,
+                                                    static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? NTT_OK : hip_fail(e, "ntt_rns_decompose launch");
+  } catch (const std::bad_alloc&) {
+    return fail(NTT_ERR_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(NTT_ERR_ARG, "unexpected failure in ntt_rns_decompose");
+  }
+}
+
+ntt_status ntt_crt_reconstruct(ntt_plan_t plan, const uint64_t* d_res, uint64_t* d_words, uint32_t n_polys,
+                               void* stream) {
+  try {
+    ntt_status s;
+    if ((s = check_data(plan, d_res, n_polys)) || (s = check_data(plan, d_words, n_polys))) return s;
+    if (plan->L > kCrtMaxLimbs)
+      return fail(NTT_ERR_UNSUPPORTED, "reconstruction takes at most " + std::to_string(kCrtMaxLimbs) + " primes");
+    if (d_res == d_words) return fail(NTT_ERR_ARG, "d_words must not alias d_res");
+    if ((s = crt_prepare(plan))) return s;
+    DeviceGuard g(plan->device);
+    if (!g.ok) return fail(NTT_ERR_HIP, "cannot select the plan's device");
+    const hipError_t e = nttk::launch_crt_reconstruct(d_res, d_words, n_polys, plan->logN, plan->L, plan->crt.W,
+                                                      plan->crt.inv, plan->crt.M, plan->crt.kQ, plan->d_q,
+                                                      static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? NTT_OK : hip_fail(e, "ntt_crt_reconstruct launch");
+  } catch (const std::bad_alloc&) {
+    return fail(NTT_ERR_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(NTT_ERR_ARG, "unexpected failure in ntt_crt_reconstruct");
   }
 }
 

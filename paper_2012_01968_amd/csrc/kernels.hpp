@@ -39,6 +39,20 @@ uint32_t stage_group_count(uint32_t logN, int log2_radix);
 hipError_t launch_stage_group(const PassArgs& a, int log2_radix, bool inverse, uint32_t g, hipStream_t st);
 hipError_t launch_stage_groups(const PassArgs& a, int log2_radix, bool inverse, hipStream_t st);
 
+// 32-bit words (kernels32.hip): primes below 2^30, tables of {w, floor(w 2^32 / q)} pairs.
+bool shape32_supported(uint32_t logN, uint32_t logN1);
+hipError_t launch_transform32(uint32_t* data, const void* tw, const void* scale, const uint32_t* q, uint64_t n_vec,
+                              uint32_t L, uint32_t logN, uint32_t logN1, bool inverse, hipStream_t st);
+hipError_t launch_pointwise32(const uint32_t* A, const uint32_t* B, uint32_t* C, const uint32_t* qs,
+                              const uint64_t* mus, uint64_t n, uint32_t logN, uint32_t L, hipStream_t st);
+
+// RNS <-> integer conversion (crt.hip): integers as [n_polys][W][N] little-endian words.
+hipError_t launch_rns_decompose(const uint64_t* words, uint32_t W, uint64_t* res, uint32_t n_polys, uint32_t logN,
+                                uint32_t L, const Tw* pow2, uint32_t pow2_stride, const uint64_t* qs, hipStream_t st);
+hipError_t launch_crt_reconstruct(const uint64_t* res, uint64_t* out, uint32_t n_polys, uint32_t logN, uint32_t L,
+                                  uint32_t W, const Tw* inv, const uint64_t* M, const uint64_t* kQ, const uint64_t* qs,
+                                  hipStream_t st);
+
 // In-place bit-reversal permutation of every vector described by `a` (slot i <-> slot
 // brv(i)): turns the forward transform's bit-reversed output into natural order and back.
 hipError_t launch_brv_permute(const PassArgs& a, hipStream_t st);

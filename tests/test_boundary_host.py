@@ -10,7 +10,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2012_01968_amd", "csrc")
 
 
-@pytest.mark.parametrize("check", ["plan_life_check", "tune_file_check"])
+@pytest.mark.parametrize("check", ["plan_life_check", "tune_file_check", "crt_math_check"])
 def test_host_check(tmp_path, check):
     exe = tmp_path / check
     subprocess.check_call(["g++", "-std=c++17", "-O2", "-Wall", "-I", CSRC,

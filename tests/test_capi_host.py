@@ -9,7 +9,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "ntt_mi355x.h")
-LIB = os.path.join(ROOT, "paper_2012_01968_amd", "libntt_mi355x.so")
+LIB = os.environ.get("NTT_MI355X_LIB") or os.path.join(ROOT, "paper_2012_01968_amd", "libntt_mi355x.so")
 
 
 def declared_functions():
@@ -53,7 +53,7 @@ class _Opts(ctypes.Structure):
                 ("ot_log2_base", ctypes.c_int32), ("log2_n1", ctypes.c_int32),
                 ("kernel_path", ctypes.c_int32), ("use_autotune", ctypes.c_int32),
                 ("tune_polys", ctypes.c_int32), ("order", ctypes.c_int32), ("log2_radix", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("word_bits", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 def _create(lib, N, primes, opts=None):
@@ -78,8 +78,14 @@ def test_argument_errors_are_synchronous(lib):
     assert _create(lib, 1 << 10, [1 + (1 << 11) * 3 * 5]) == (-3, None)  # 30721 = 31*991: composite, 1 mod 2N
     assert _create(lib, 1 << 10, []) == (-1, None)
     o = _Opts()
-    o.reserved[1] = 1
+    o.reserved = 1
     assert _create(lib, 1 << 10, [q], o) == (-1, None)
+    o = _Opts(0, 0, 0, 0, 0, 0, 0, 0, 0, 16)
+    assert _create(lib, 1 << 10, [q], o) == (-1, None)             # word_bits is 0, 32 or 64
+    o = _Opts(0, 0, 0, 0, 0, 0, 0, 0, 0, 32)
+    assert _create(lib, 1 << 10, [q], o) == (-3, None)             # 32-bit words need q < 2^30
+    o = _Opts(2, 2, 10, 0, 0, 0, 0, 0, 0, 32)
+    assert _create(lib, 1 << 16, [(1 << 29) + 1], o) == (-6, None) # 32-bit plans take table twiddles
     o = _Opts(0, 0, 0, 0, 0, 0, 0, 2)
     assert _create(lib, 1 << 10, [q], o) == (-1, None)             # order is BITREV or NATURAL
     o = _Opts(0, 0, 0, 0, 0, 2)
