@@ -527,7 +527,8 @@ def uneven_batch_bench(args):
            "polys_by_logN": {int(k): int((logNs == k).sum()) for k in cfg["logNs"]},
            "plans": plan_names}
     steps = max(5, min(args.steps, 40))
-    for name, mode in (("plain", ntt.BATCH_PLAIN), ("grouped", ntt.BATCH_GROUPED), ("graph", ntt.BATCH_GRAPH)):
+    for name, mode in (("plain", ntt.BATCH_PLAIN), ("grouped", ntt.BATCH_GROUPED), ("graph", ntt.BATCH_GRAPH),
+                       ("graph_branched", ntt.BATCH_GRAPH_BRANCHED)):
         ramp(lambda i: ntt.ntt_batch_run(batch, mode), args.ramp_ms)
         for _ in range(3):
             ntt.ntt_batch_run(batch, mode)
@@ -553,9 +554,10 @@ def uneven_batch_bench(args):
     ok = all(torch.equal(b, src[k][:L]) for b, k, L in zip(bufs, logNs.tolist(), Ls.tolist()))
     out["roundtrip_ok"] = bool(ok)
     out["matches_oracle"] = uneven_forward_matches_oracle(plans, src, chain, logNs, Ls, Lmax)
-    log(f"[uneven] forward of all {cfg['polys']} polys (grouped and graph runs) "
+    log(f"[uneven] forward of all {cfg['polys']} polys (grouped and both graph runs) "
         f"{'matches' if out['matches_oracle'] else 'DIFFERS FROM'} the oracle")
     out["graph_vs_plain"] = round(out["plain"]["ms_per_step"] / out["graph"]["ms_per_step"], 3)
+    out["branched_vs_plain"] = round(out["plain"]["ms_per_step"] / out["graph_branched"]["ms_per_step"], 3)
     batch.destroy()
     for p in plans.values():
         p.destroy()
@@ -575,7 +577,7 @@ def uneven_jobs(cfg=None):
 
 def uneven_forward_matches_oracle(plans, src, chain, logNs, Ls, Lmax) -> bool:
     """Forward NTT of every polynomial of the uneven batch (one batch of forward jobs, run
-    grouped and replayed from its graph) against the oracle.  Each polynomial is the first L
+    grouped and replayed from its sequential and its branched graph) against the oracle.  Each polynomial is the first L
     limbs of its size's source polynomial, so the expected output is the first L limbs of the
     oracle's forward transform of that source."""
     import torch
@@ -585,7 +587,7 @@ def uneven_forward_matches_oracle(plans, src, chain, logNs, Ls, Lmax) -> bool:
     want = {k: oracle.forward(src[k].cpu().numpy().view(np.uint64), chain, oracle.roots(chain, 1 << k),
                               max(1, min(16, os.cpu_count() or 1))) for k in plans}
     ok = True
-    for mode in (ntt.BATCH_GROUPED, ntt.BATCH_GRAPH):
+    for mode in (ntt.BATCH_GROUPED, ntt.BATCH_GRAPH, ntt.BATCH_GRAPH_BRANCHED):
         bufs, jobs = [], []
         for k, L in zip(logNs.tolist(), Ls.tolist()):
             b = src[k][:L].clone()

@@ -220,7 +220,11 @@ ntt_status ntt_polymul_negacyclic(ntt_plan_t plan, const uint64_t* d_a, const ui
  *                      (vector-list launches: all forward work, then all key products, then
  *                      all inverse work);
  *   NTT_BATCH_GRAPH    the GROUPED launches captured once into a hipGraph (on a stream the
- *                      batch owns) and replayed on the caller's stream on every run.
+ *                      batch owns) and replayed on the caller's stream on every run;
+ *   NTT_BATCH_GRAPH_BRANCHED  the same launches captured as up to four independent
+ *                      branches of one graph (each plan's forward, key-product and inverse
+ *                      launches in one branch, plans balanced over the branches by work),
+ *                      so that on the device the launches of different sizes overlap.
  *
  * op is a set of steps run in the order forward, key product, inverse: NTT_OP_MULKEY
  * multiplies every polynomial of the job element-wise by the job's key, a device array
@@ -230,7 +234,7 @@ ntt_status ntt_polymul_negacyclic(ntt_plan_t plan, const uint64_t* d_a, const ui
  * jobs name (see ntt_plan_destroy), so a plan may be destroyed before the batch; the data
  * arrays must stay valid and may not overlap between jobs. */
 enum { NTT_OP_FORWARD = 1, NTT_OP_INVERSE = 2, NTT_OP_FORWARD_INVERSE = 3, NTT_OP_MULKEY = 4 };
-enum { NTT_BATCH_PLAIN = 0, NTT_BATCH_GROUPED = 1, NTT_BATCH_GRAPH = 2 };
+enum { NTT_BATCH_PLAIN = 0, NTT_BATCH_GROUPED = 1, NTT_BATCH_GRAPH = 2, NTT_BATCH_GRAPH_BRANCHED = 3 };
 
 typedef struct {
     ntt_plan_t plan;

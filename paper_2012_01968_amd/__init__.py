@@ -20,7 +20,7 @@ __all__ = [
     "ntt_plan_order", "ORDER_BITREV", "ORDER_NATURAL",
     "ntt_pointwise_mul", "ntt_polymul_negacyclic", "ntt_status_string",
     "Batch", "ntt_batch_create", "ntt_batch_run", "ntt_batch_destroy", "ntt_batch_assign", "OP_FORWARD", "OP_INVERSE",
-    "OP_FORWARD_INVERSE", "OP_MULKEY", "BATCH_PLAIN", "BATCH_GROUPED", "BATCH_GRAPH",
+    "OP_FORWARD_INVERSE", "OP_MULKEY", "BATCH_PLAIN", "BATCH_GROUPED", "BATCH_GRAPH", "BATCH_GRAPH_BRANCHED",
     "library_path", "TWIDDLE_AUTO", "TWIDDLE_TABLE", "TWIDDLE_OT", "PATH_AUTO", "PATH_SPLIT", "PATH_FUSED",
     "PATH_RADIX2", "PATH_REGISTER", "ntt_plan_log2_radix", "ntt_forward_u32", "ntt_inverse_u32",
     "ntt_pointwise_mul_u32", "ntt_polymul_negacyclic_u32", "ntt_plan_word_bits", "ntt_crt_words",
@@ -30,7 +30,7 @@ __all__ = [
 TWIDDLE_AUTO, TWIDDLE_TABLE, TWIDDLE_OT = 0, 1, 2
 PATH_AUTO, PATH_SPLIT, PATH_FUSED, PATH_RADIX2, PATH_REGISTER = 0, 1, 2, 3, 4
 OP_FORWARD, OP_INVERSE, OP_FORWARD_INVERSE, OP_MULKEY = 1, 2, 3, 4
-BATCH_PLAIN, BATCH_GROUPED, BATCH_GRAPH = 0, 1, 2
+BATCH_PLAIN, BATCH_GROUPED, BATCH_GRAPH, BATCH_GRAPH_BRANCHED = 0, 1, 2, 3
 ORDER_BITREV, ORDER_NATURAL = 0, 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))

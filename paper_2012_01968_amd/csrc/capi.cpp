@@ -637,12 +637,23 @@ struct ntt_batch_s {
   hipStream_t capture_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // NTT_BATCH_GRAPH_BRANCHED: its own graph, the streams the branches are captured on and the
+  // fork / join events (created on first use, kept for the batch's life)
+  hipGraph_t graph_br = nullptr;
+  hipGraphExec_t exec_br = nullptr;
+  std::vector<hipStream_t> branch_streams;
+  std::vector<hipEvent_t> branch_events;   // [0]: fork; [1 + k]: join of branch k + 1
+  static constexpr int kBranches = 4;
 
   void drop_graph() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
+    if (exec_br) (void)hipGraphExecDestroy(exec_br);
+    if (graph_br) (void)hipGraphDestroy(graph_br);
     exec = nullptr;
     graph = nullptr;
+    exec_br = nullptr;
+    graph_br = nullptr;
   }
 
   ~ntt_batch_s() {
@@ -653,6 +664,8 @@ struct ntt_batch_s {
     }
     drop_graph();
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    for (hipStream_t bs : branch_streams) (void)hipStreamDestroy(bs);
+    for (hipEvent_t ev : branch_events) (void)hipEventDestroy(ev);
     if (d_desc) (void)hipFree(d_desc);
     if (h_desc) (void)hipHostFree(h_desc);
     hold({});
@@ -686,36 +699,103 @@ struct ntt_batch_s {
   hipError_t grouped(hipStream_t st) const {
     for (int phase = 0; phase < 3; ++phase) {
       for (const Group& g : groups) {
-        const int ot = g.plan->active_ot();
-        const bool split = g.plan->logN1 != 0;
-        hipError_t e = hipSuccess;
-        if (phase == 1) {
-          if (g.n_key &&
-              (e = nttk::launch_pointwise_list(at(g.off_key), g.n_key, g.plan->logN, g.plan->d_q, g.plan->d_mu,
-                                               g.plan->d_bits, st)) != hipSuccess)
-            return e;
-          if (g.n_full &&
-              (e = nttk::launch_mul_rows(list_args(g, g.off_full, g.n_full, false),
-                                         list_args(g, g.off_full, g.n_full, true), ot, st)) != hipSuccess)
-            return e;
-          continue;
-        }
-        const bool inv = phase == 2;
-        const uint64_t n = inv ? g.n_inv : g.n_fwd;
-        if (n) {
-          const PassArgs a = list_args(g, inv ? g.off_inv : g.off_fwd, n, inv);
-          const bool nat = g.plan->order == NTT_ORDER_NATURAL;
-          if (nat && inv && (e = nttk::launch_brv_permute(a, st)) != hipSuccess) return e;
-          if ((e = enqueue_direction(g.plan, a, inv, st)) != hipSuccess) return e;
-          if (nat && !inv && (e = nttk::launch_brv_permute(a, st)) != hipSuccess) return e;
-        }
-        if (g.n_full && split) {
-          const PassArgs a = list_args(g, g.off_full, g.n_full, inv);
-          if ((e = inv ? nttk::launch_inverse_pass(a, ot, 1, st) : nttk::launch_forward_pass(a, ot, 0, st)) !=
-              hipSuccess)
-            return e;
-        }
+        const hipError_t e = group_phase(g, phase, st);
+        if (e != hipSuccess) return e;
       }
+    }
+    return hipSuccess;
+  }
+
+  // Phase `phase` (0 forward, 1 key products, 2 inverse) of one plan's vectors.
+  hipError_t group_phase(const Group& g, int phase, hipStream_t st) const {
+    const int ot = g.plan->active_ot();
+    const bool split = g.plan->logN1 != 0;
+    hipError_t e = hipSuccess;
+    if (phase == 1) {
+      if (g.n_key &&
+          (e = nttk::launch_pointwise_list(at(g.off_key), g.n_key, g.plan->logN, g.plan->d_q, g.plan->d_mu,
+                                           g.plan->d_bits, st)) != hipSuccess)
+        return e;
+      if (g.n_full &&
+          (e = nttk::launch_mul_rows(list_args(g, g.off_full, g.n_full, false),
+                                     list_args(g, g.off_full, g.n_full, true), ot, st)) != hipSuccess)
+        return e;
+      return hipSuccess;
+    }
+    const bool inv = phase == 2;
+    const uint64_t n = inv ? g.n_inv : g.n_fwd;
+    if (n) {
+      const PassArgs a = list_args(g, inv ? g.off_inv : g.off_fwd, n, inv);
+      const bool nat = g.plan->order == NTT_ORDER_NATURAL;
+      if (nat && inv && (e = nttk::launch_brv_permute(a, st)) != hipSuccess) return e;
+      if ((e = enqueue_direction(g.plan, a, inv, st)) != hipSuccess) return e;
+      if (nat && !inv && (e = nttk::launch_brv_permute(a, st)) != hipSuccess) return e;
+    }
+    if (g.n_full && split) {
+      const PassArgs a = list_args(g, g.off_full, g.n_full, inv);
+      if ((e = inv ? nttk::launch_inverse_pass(a, ot, 1, st) : nttk::launch_forward_pass(a, ot, 0, st)) !=
+          hipSuccess)
+        return e;
+    }
+    return hipSuccess;
+  }
+
+  // Work of a group, in butterflies: what the branches are balanced by.
+  static double group_work(const Group& g) {
+    const double vecs = (double)(g.n_fwd + g.n_inv + 2 * g.n_full) + 0.1 * (double)g.n_key;
+    return vecs * (double)g.plan->N * (double)g.plan->logN;
+  }
+
+  // Branch of each group: groups sorted by work, each to the least loaded of the branches.
+  std::vector<int> branch_of_groups(int nb) const {
+    std::vector<size_t> order(groups.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::sort(order.begin(), order.end(),
+              [&](size_t x, size_t y) { return group_work(groups[x]) > group_work(groups[y]); });
+    std::vector<double> load(nb, 0.0);
+    std::vector<int> br(groups.size(), 0);
+    for (size_t i : order) {
+      const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      br[i] = k;
+      load[k] += group_work(groups[i]);
+    }
+    return br;
+  }
+
+  // The groups' chains as independent branches: branch 0 on `st`, branches 1.. on the
+  // batch's own streams after a fork event, joined back into `st` by one event each.  Every
+  // group's vectors are its own (jobs may not overlap), so the branches need no ordering
+  // among themselves; on the device, small sizes then run beside the large ones.
+  hipError_t branched(hipStream_t st) {
+    const int nb = (int)std::min<size_t>(kBranches, groups.size());
+    hipError_t e;
+    while ((int)branch_streams.size() < nb - 1) {
+      hipStream_t s = nullptr;
+      if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess) return e;
+      branch_streams.push_back(s);
+    }
+    while ((int)branch_events.size() < nb) {
+      hipEvent_t ev = nullptr;
+      if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
+      branch_events.push_back(ev);
+    }
+    const std::vector<int> br = branch_of_groups(nb);
+    if (nb > 1) {
+      if ((e = hipEventRecord(branch_events[0], st)) != hipSuccess) return e;
+      for (int k = 1; k < nb; ++k)
+        if ((e = hipStreamWaitEvent(branch_streams[k - 1], branch_events[0], 0)) != hipSuccess) return e;
+    }
+    for (int k = 0; k < nb; ++k) {
+      hipStream_t s = k ? branch_streams[k - 1] : st;
+      for (size_t i = 0; i < groups.size(); ++i) {
+        if (br[i] != k) continue;
+        for (int phase = 0; phase < 3; ++phase)
+          if ((e = group_phase(groups[i], phase, s)) != hipSuccess) return e;
+      }
+    }
+    for (int k = 1; k < nb; ++k) {
+      if ((e = hipEventRecord(branch_events[k], branch_streams[k - 1])) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(st, branch_events[k], 0)) != hipSuccess) return e;
     }
     return hipSuccess;
   }
@@ -1099,7 +1179,7 @@ ntt_status ntt_batch_run(ntt_batch_t b, int32_t mode, void* stream) {
     if (!g.ok) return fail(NTT_ERR_HIP, "cannot select the batch's device");
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e = hipSuccess;
-    if (mode < NTT_BATCH_PLAIN || mode > NTT_BATCH_GRAPH) return fail(NTT_ERR_ARG, "unknown batch mode");
+    if (mode < NTT_BATCH_PLAIN || mode > NTT_BATCH_GRAPH_BRANCHED) return fail(NTT_ERR_ARG, "unknown batch mode");
     if (b->jobs.empty()) return NTT_OK;   // emptied by a failed assign
     if (mode == NTT_BATCH_PLAIN) {
       for (const ntt_job& job : b->jobs) {
@@ -1144,6 +1224,32 @@ ntt_status ntt_batch_run(ntt_batch_t b, int32_t mode, void* stream) {
         }
       }
       e = hipGraphLaunch(b->exec, st);
+    } else if (mode == NTT_BATCH_GRAPH_BRANCHED) {
+      if (!b->exec_br) {
+        if (!b->capture_stream &&
+            (e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking)) != hipSuccess) {
+          b->capture_stream = nullptr;
+          return hip_fail(e, "creating the capture stream");
+        }
+        if (b->graph_br) (void)hipGraphDestroy(b->graph_br);
+        b->graph_br = nullptr;
+        if ((e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+          return hip_fail(e, "hipStreamBeginCapture");
+        const hipError_t le = b->branched(b->capture_stream);
+        e = hipStreamEndCapture(b->capture_stream, &b->graph_br);
+        if (le != hipSuccess || e != hipSuccess) {
+          if (b->graph_br) (void)hipGraphDestroy(b->graph_br);
+          b->graph_br = nullptr;
+          return hip_fail(le != hipSuccess ? le : e, le != hipSuccess ? "capturing the batch" : "hipStreamEndCapture");
+        }
+        if ((e = hipGraphInstantiate(&b->exec_br, b->graph_br, nullptr, nullptr, 0)) != hipSuccess) {
+          b->exec_br = nullptr;
+          (void)hipGraphDestroy(b->graph_br);
+          b->graph_br = nullptr;
+          return hip_fail(e, "hipGraphInstantiate");
+        }
+      }
+      e = hipGraphLaunch(b->exec_br, st);
     } else {
       return fail(NTT_ERR_ARG, "unknown batch mode");
     }

@@ -226,6 +226,8 @@ def uniform_wide(seed: int, poly: int, bound: int, n: int) -> np.ndarray:
             v = out[w, todo]
             less |= eq & (v < bw[w])
             eq &= v == bw[w]
+        if bound == 1 << (64 * W):   # every W-word draw lies below the bound
+            less[:] = True
         todo = todo[~less]
         attempt += 1
         if attempt > 200:

@@ -394,7 +394,7 @@ def test_plan_reuse_across_streams():
 
 # ------------------------------------------------------------------ batches of uneven jobs
 
-@pytest.mark.parametrize("mode", ["plain", "grouped", "graph"])
+@pytest.mark.parametrize("mode", ["plain", "grouped", "graph", "branched"])
 def test_batch_uneven_jobs(mode):
     """Jobs of several N and limb counts (prefixes of one prime chain), mixed ops, in one
     batch; every job is checked against the oracle and the three run modes agree."""
@@ -422,12 +422,13 @@ def test_batch_uneven_jobs(mode):
             want.append(w)
             jobs.append((plans[logN], d, polys, limbs if limbs < len(chain) else 0, op))
         batch = ntt.ntt_batch_create(jobs)
-        m = {"plain": ntt.BATCH_PLAIN, "grouped": ntt.BATCH_GROUPED, "graph": ntt.BATCH_GRAPH}[mode]
+        m = {"plain": ntt.BATCH_PLAIN, "grouped": ntt.BATCH_GROUPED, "graph": ntt.BATCH_GRAPH,
+             "branched": ntt.BATCH_GRAPH_BRANCHED}[mode]
         ntt.ntt_batch_run(batch, m)
         torch.cuda.synchronize()
         for d, w in zip(bufs, want):
             assert np.array_equal(host(d), w)
-        if mode == "graph":   # replays: forward-only jobs advance, round-trip jobs stay put
+        if mode in ("graph", "branched"):   # replays: forward-only jobs advance, round-trip jobs stay put
             for _ in range(3):
                 ntt.ntt_batch_run(batch, m)
                 torch.cuda.synchronize()
@@ -440,7 +441,7 @@ def test_batch_uneven_jobs(mode):
             p.destroy()
 
 
-@pytest.mark.parametrize("mode", ["plain", "grouped", "graph"])
+@pytest.mark.parametrize("mode", ["plain", "grouped", "graph", "branched"])
 def test_batch_mulkey_jobs(mode):
     """Forward, product with a resident NTT-domain key, inverse, as one job: the result is
     the negacyclic product with the key polynomial, per limb (schoolbook-checked on a small
@@ -478,7 +479,8 @@ def test_batch_mulkey_jobs(mode):
             jobs.append((plans[logN], d, polys, limbs if limbs < len(chain) else 0,
                          ntt.OP_FORWARD | ntt.OP_MULKEY | ntt.OP_INVERSE, dk))
         batch = ntt.ntt_batch_create(jobs)
-        m = {"plain": ntt.BATCH_PLAIN, "grouped": ntt.BATCH_GROUPED, "graph": ntt.BATCH_GRAPH}[mode]
+        m = {"plain": ntt.BATCH_PLAIN, "grouped": ntt.BATCH_GROUPED, "graph": ntt.BATCH_GRAPH,
+             "branched": ntt.BATCH_GRAPH_BRANCHED}[mode]
         ntt.ntt_batch_run(batch, m)
         torch.cuda.synchronize()
         for (d, _), w in zip(bufs, want):
@@ -540,7 +542,7 @@ def test_config3_polymul_entry_point():
         plan.destroy()
 
 
-@pytest.mark.parametrize("mode", ["plain", "grouped", "graph"])
+@pytest.mark.parametrize("mode", ["plain", "grouped", "graph", "branched"])
 def test_batch_mulkey_ot_and_wide_plans(mode):
     """Forward, key product, inverse jobs on OT plans (single pass and split) and on a plan of
     61-bit primes (exact quotients), with limb prefixes; every result against the oracle."""
@@ -570,7 +572,8 @@ def test_batch_mulkey_ot_and_wide_plans(mode):
                 jobs.append((plan, d, polys, limbs if limbs < 4 else 0,
                              ntt.OP_FORWARD | ntt.OP_MULKEY | ntt.OP_INVERSE, dk))
         batch = ntt.ntt_batch_create(jobs)
-        m = {"plain": ntt.BATCH_PLAIN, "grouped": ntt.BATCH_GROUPED, "graph": ntt.BATCH_GRAPH}[mode]
+        m = {"plain": ntt.BATCH_PLAIN, "grouped": ntt.BATCH_GROUPED, "graph": ntt.BATCH_GRAPH,
+             "branched": ntt.BATCH_GRAPH_BRANCHED}[mode]
         ntt.ntt_batch_run(batch, m)
         torch.cuda.synchronize()
         for (d, _), w in zip(bufs, want):
@@ -581,7 +584,7 @@ def test_batch_mulkey_ot_and_wide_plans(mode):
             p.destroy()
 
 
-@pytest.mark.parametrize("mode", ["grouped", "graph"])
+@pytest.mark.parametrize("mode", ["grouped", "graph", "branched"])
 def test_config4_full_uneven_batch(mode):
     """The full uneven workload (256 polys, N from 2^13 to 2^17, L uniform in [4, 60], seed 4)
     with the plans the benchmark builds for it (the tuner's cached choice per size, else the
@@ -602,7 +605,7 @@ def test_config4_full_uneven_batch(mode):
             s = synth.residue_batch(cfg["seed"] + k, chain, 1 << k, 1).reshape(Lmax, 1 << k)
             src[k] = s
             want[k] = oracle.forward(s, chain, oracle.roots(chain, 1 << k), THREADS)
-        m = ntt.BATCH_GROUPED if mode == "grouped" else ntt.BATCH_GRAPH
+        m = {"grouped": ntt.BATCH_GROUPED, "graph": ntt.BATCH_GRAPH, "branched": ntt.BATCH_GRAPH_BRANCHED}[mode]
         for op in (ntt.OP_FORWARD, ntt.OP_FORWARD_INVERSE):
             bufs, jobs = [], []
             for k, L in zip(logNs.tolist(), Ls.tolist()):
