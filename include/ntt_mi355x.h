@@ -207,6 +207,20 @@ ntt_status ntt_pointwise_mul(ntt_plan_t plan, const uint64_t* d_a, const uint64_
 ntt_status ntt_polymul_negacyclic(ntt_plan_t plan, const uint64_t* d_a, const uint64_t* d_b, uint64_t* d_c,
                                   uint32_t n_polys, void* stream);
 
+/* The same product for callers that cannot allocate device memory (code under graph
+ * capture, tight serving loops, hosts that forbid hipMalloc): identical arguments, result
+ * and launches as ntt_polymul_negacyclic, but NTT(b) goes to one fixed 64 MiB device array
+ * that the library holds on every device it runs on until the process ends, so the call
+ * allocates nothing.  n_polys*L*N must not exceed ntt_polymul_noalloc_max_words() (2^23
+ * residues), else NTT_ERR_ARG and nothing is enqueued; larger batches go in several calls.
+ * Every call on one device shares that array: calls whose work overlaps on the device
+ * (different streams, or different host threads without ordering) race and give wrong
+ * results.  Calls on one stream are ordered and safe.  The array is fully written before it
+ * is read, so no call depends on what an earlier one left there. */
+ntt_status ntt_polymul_negacyclic_noalloc(ntt_plan_t plan, const uint64_t* d_a, const uint64_t* d_b, uint64_t* d_c,
+                                          uint32_t n_polys, void* stream);
+uint64_t ntt_polymul_noalloc_max_words(void);
+
 /* ---------------------------------------------------------------- batches of uneven jobs
  *
  * Many polynomials of different N and limb counts (Section VI-A's batching, taken to

@@ -24,7 +24,7 @@ __all__ = [
     "library_path", "TWIDDLE_AUTO", "TWIDDLE_TABLE", "TWIDDLE_OT", "PATH_AUTO", "PATH_SPLIT", "PATH_FUSED",
     "PATH_RADIX2", "PATH_REGISTER", "ntt_plan_log2_radix", "ntt_forward_u32", "ntt_inverse_u32",
     "ntt_pointwise_mul_u32", "ntt_polymul_negacyclic_u32", "ntt_plan_word_bits", "ntt_crt_words",
-    "ntt_rns_decompose", "ntt_crt_reconstruct",
+    "ntt_rns_decompose", "ntt_crt_reconstruct", "ntt_polymul_negacyclic_noalloc", "ntt_polymul_noalloc_max_words",
 ]
 
 TWIDDLE_AUTO, TWIDDLE_TABLE, TWIDDLE_OT = 0, 1, 2
@@ -108,6 +108,9 @@ _lib.ntt_plan_log2_radix.restype = ctypes.c_int32
 _lib.ntt_plan_tuned.restype = ctypes.c_int32
 _lib.ntt_pointwise_mul.argtypes = [_vp, _vp, _vp, _vp, _u32, _vp]
 _lib.ntt_polymul_negacyclic.argtypes = [_vp, _vp, _vp, _vp, _u32, _vp]
+_lib.ntt_polymul_negacyclic_noalloc.argtypes = [_vp, _vp, _vp, _vp, _u32, _vp]
+_lib.ntt_polymul_noalloc_max_words.argtypes = []
+_lib.ntt_polymul_noalloc_max_words.restype = ctypes.c_uint64
 for _f in ("ntt_forward_u32", "ntt_inverse_u32"):
     getattr(_lib, _f).argtypes = [_vp, _vp, _u32, _vp]
     getattr(_lib, _f).restype = ctypes.c_int
@@ -309,6 +312,19 @@ def ntt_pointwise_mul(plan: Plan, a, b, c, n_polys: int | None = None, stream=No
 def ntt_polymul_negacyclic(plan: Plan, a, b, c, n_polys: int | None = None, stream=None) -> None:
     n, (pa, pb, pc) = _batch_addrs(plan, [a, b, c], ["a", "b", "c"], n_polys)
     _check(_lib.ntt_polymul_negacyclic(plan.handle, pa, pb, pc, n, _stream(stream)), "ntt_polymul_negacyclic")
+
+
+def ntt_polymul_negacyclic_noalloc(plan: Plan, a, b, c, n_polys: int | None = None, stream=None) -> None:
+    """ntt_polymul_negacyclic with NTT(b) in the library's fixed device array: allocates
+    nothing; at most ntt_polymul_noalloc_max_words() residues per call; calls that overlap
+    on one device race."""
+    n, (pa, pb, pc) = _batch_addrs(plan, [a, b, c], ["a", "b", "c"], n_polys)
+    _check(_lib.ntt_polymul_negacyclic_noalloc(plan.handle, pa, pb, pc, n, _stream(stream)),
+           "ntt_polymul_negacyclic_noalloc")
+
+
+def ntt_polymul_noalloc_max_words() -> int:
+    return int(_lib.ntt_polymul_noalloc_max_words())
 
 
 # ---------------------------------------------------------------- 32-bit words

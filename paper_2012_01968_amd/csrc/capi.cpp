@@ -1121,6 +1121,55 @@ ntt_status ntt_polymul_negacyclic(ntt_plan_t plan, const uint64_t* d_a, const ui
   }
 }
 
+// ---------------------------------------------------------------- product without allocation
+// For callers that cannot allocate device memory (graph capture, serving loops): NTT(b) goes
+// to a fixed device array instead of a plan-owned buffer.  Each device that loads the library
+// holds its own copy of the array until the process ends.  In host code `scratch` names a
+// host-side stand-in, not device memory, so the array's device address is looked up once per
+// device (scratch_address) and only that address is ever passed on.
+static constexpr size_t kNoAllocScratchWords = (size_t)1 << 23;   // 64 MiB
+static __device__ __align__(256) uint64_t scratch[kNoAllocScratchWords];
+
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static uint64_t* g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on `dev`, which must be the current device.
+static ntt_status scratch_address(int dev, uint64_t** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(NTT_ERR_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = static_cast<uint64_t*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return NTT_OK;
+}
+
+uint64_t ntt_polymul_noalloc_max_words(void) { return kNoAllocScratchWords; }
+
+ntt_status ntt_polymul_negacyclic_noalloc(ntt_plan_t plan, const uint64_t* d_a, const uint64_t* d_b, uint64_t* d_c,
+                                          uint32_t n_polys, void* stream) {
+  try {
+    ntt_status s = check_product(plan, d_a, d_b, d_c, n_polys);
+    if (s != NTT_OK) return s;
+    const uint64_t words = (uint64_t)n_polys * plan->L * plan->N;
+    if (words > kNoAllocScratchWords)
+      return fail(NTT_ERR_ARG, "n_polys*L*N = " + std::to_string(words) + " exceeds the no-allocation limit of " +
+                                   std::to_string(kNoAllocScratchWords) + " residues");
+    DeviceGuard g(plan->device);
+    if (!g.ok) return fail(NTT_ERR_HIP, "cannot select the plan's device");
+    uint64_t* tmp = nullptr;
+    if ((s = scratch_address(plan->device, &tmp)) != NTT_OK) return s;
+    const hipError_t e = polymul_enqueue(plan, d_a, d_b, d_c, n_polys, tmp, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? NTT_OK : hip_fail(e, "ntt_polymul_negacyclic_noalloc launch");
+  } catch (...) {
+    return fail(NTT_ERR_ARG, "unexpected failure in ntt_polymul_negacyclic_noalloc");
+  }
+}
+
 ntt_status ntt_batch_create(ntt_batch_t* out, const ntt_job* jobs, uint32_t n_jobs) {
   try {
     if (!out) return fail(NTT_ERR_ARG, "out is NULL");
