@@ -63,7 +63,8 @@ def ramp(step, ms: float) -> None:
 def variant_key(info: dict, ots: int) -> str:
     """Name of a plan configuration, as used by the traffic summary."""
     path = "fused" if info["kernel_path"] == 2 else "split"
-    return f"{'ot%d' % ots if ots else 'table'}-{path}-n1={info['log2_n1']}"
+    tiles = "".join(f"-{k}={info[k]}" for k in ("r1", "wg_size", "col_width") if info.get(k))
+    return f"{'ot%d' % ots if ots else 'table'}-{path}-n1={info['log2_n1']}{tiles}"
 
 
 def tune_shape(N: int, primes, polys: int) -> dict:

@@ -78,6 +78,10 @@ typedef struct {
     int32_t order;          /* NTT_ORDER_*: slot order of the NTT domain (see below)     */
     int32_t log2_radix;     /* NTT_PATH_REGISTER: stages per launch, 2..5; 0 = 4         */
     int32_t word_bits;      /* residue word: 0 or 64 = uint64_t, 32 = uint32_t (below)   */
+    int32_t r1;             /* row pass values per lane (per-thread NTT size): 0 = 8, 4, 8 */
+    int32_t wg_size;        /* row pass workgroup lanes: 0 = 128, 64, 128, 256           */
+    int32_t col_width;      /* column pass tile width in adjacent columns: 0 = automatic, */
+                            /* 16, 32, 64 (at most N2; longer columns take fewer)        */
     int32_t reserved;       /* must be zero                                             */
 } ntt_plan_opts;
 
@@ -95,12 +99,18 @@ enum { NTT_ORDER_BITREV = 0, NTT_ORDER_NATURAL = 1 };
  * by measurement).  The Python tuner (paper_2012_01968_amd/autotune.py) writes its choices to
  * a text file, one line per shape:
  *   <arch>:<CUs>CU <kernel source hash> <N> <L> <P> <prime bits> <log2_n1> <twiddle_mode>
- *   <ot_stages> <ot_log2_base> <kernel_path>
+ *   <ot_stages> <ot_log2_base> <kernel_path> [<r1> <wg_size> <col_width>]
  * With use_autotune = 1, ntt_plan_create reads $NTT_TUNE_FILE, else tune_cache.txt in the
  * library's directory, and takes the line for the current device, the kernels this library
  * was built from, N and the primes' width: the one with L and P = tune_polys if present, else
  * the one whose L*P is nearest.  No line (or no file) leaves the defaults; that is not an
- * error.  ntt_plan_tuned reports which happened. */
+ * error.  ntt_plan_tuned reports which happened.
+ *
+ * Debug modes.  When NTT_DEBUG is set at plan creation and holds "poison", the plan's column
+ * and row passes fill their LDS with a poison pattern before use; with "reverse", their
+ * workgroups take the tiles in reverse order.  Results must not change in either mode (no
+ * exchange reads a slot it did not write; no tile depends on another).  Other paths ignore
+ * NTT_DEBUG. */
 
 /* Kernel paths for two-pass plans.  SPLIT launches the column pass and the row pass as
  * two kernels.  FUSED runs both in one persistent launch whose workgroups drain
@@ -150,6 +160,11 @@ ntt_status ntt_plan_get_roots(ntt_plan_t plan, uint64_t* psi_out);
  * NULL. */
 ntt_status ntt_plan_get_info(ntt_plan_t plan, uint32_t* N, uint32_t* L, uint32_t* log2_n1,
                              int32_t* twiddle_mode, int32_t* ot_stages, int32_t* kernel_path);
+
+/* The tile shape the plan was created with (r1, wg_size, col_width of ntt_plan_opts; 0 where
+ * the built-in default applies: 8 values per lane, 128-lane row workgroups, and 64 columns
+ * per column tile where N2 holds them, else 16).  Any pointer may be NULL. */
+ntt_status ntt_plan_get_tiles(ntt_plan_t plan, int32_t* r1, int32_t* wg_size, int32_t* col_width);
 
 /* In-place forward NTT of every vector of d_data ([n_polys][L][N] uint64, device).
  * Section III-A merged-twist transform computed as Algorithm 1 (Cooley-Tukey with the

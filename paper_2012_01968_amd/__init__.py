@@ -74,7 +74,8 @@ class _Opts(ctypes.Structure):
                 ("ot_log2_base", ctypes.c_int32), ("log2_n1", ctypes.c_int32),
                 ("kernel_path", ctypes.c_int32), ("use_autotune", ctypes.c_int32),
                 ("tune_polys", ctypes.c_int32), ("order", ctypes.c_int32), ("log2_radix", ctypes.c_int32),
-                ("word_bits", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("word_bits", ctypes.c_int32), ("r1", ctypes.c_int32), ("wg_size", ctypes.c_int32),
+                ("col_width", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p
@@ -94,6 +95,8 @@ _lib.ntt_plan_get_roots.argtypes = [_vp, _u64p]
 _lib.ntt_plan_get_info.argtypes = [_vp, ctypes.POINTER(_u32), ctypes.POINTER(_u32), ctypes.POINTER(_u32),
                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int32)]
+_lib.ntt_plan_get_tiles.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_int32)]
 _lib.ntt_forward.argtypes = [_vp, _vp, _u32, _vp]
 _lib.ntt_inverse.argtypes = [_vp, _vp, _u32, _vp]
 _lib.ntt_forward_pass.argtypes = [_vp, _vp, _u32, _u32, _vp]
@@ -227,11 +230,12 @@ def _batch_addrs(plan: Plan, bufs, names, n_polys, esize: int = 8):
 
 def ntt_plan_create(N: int, primes, *, twiddle_mode: int = 0, ot_stages: int = 0, ot_log2_base: int = 0,
                     log2_n1: int = 0, kernel_path: int = 0, use_autotune: int = 0, tune_polys: int = 0,
-                    order: int = 0, log2_radix: int = 0, word_bits: int = 0) -> Plan:
+                    order: int = 0, log2_radix: int = 0, word_bits: int = 0, r1: int = 0, wg_size: int = 0,
+                    col_width: int = 0) -> Plan:
     primes = [int(q) for q in primes]
     arr = (ctypes.c_uint64 * len(primes))(*primes)
     opts = _Opts(twiddle_mode, ot_stages, ot_log2_base, log2_n1, kernel_path, int(use_autotune), int(tune_polys),
-                 int(order), int(log2_radix), int(word_bits))
+                 int(order), int(log2_radix), int(word_bits), int(r1), int(wg_size), int(col_width))
     h = _vp()
     _check(_lib.ntt_plan_create(ctypes.byref(h), N, arr, len(primes), ctypes.byref(opts)), "ntt_plan_create")
     return Plan(h.value, N, len(primes))
@@ -252,8 +256,11 @@ def ntt_plan_get_info(plan: Plan) -> dict:
     mode, ots, path = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     _check(_lib.ntt_plan_get_info(plan.handle, ctypes.byref(N), ctypes.byref(L), ctypes.byref(n1),
                                   ctypes.byref(mode), ctypes.byref(ots), ctypes.byref(path)), "ntt_plan_get_info")
+    r1, wg, cw = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.ntt_plan_get_tiles(plan.handle, ctypes.byref(r1), ctypes.byref(wg), ctypes.byref(cw)),
+           "ntt_plan_get_tiles")
     return {"N": N.value, "L": L.value, "log2_n1": n1.value, "twiddle_mode": mode.value, "ot_stages": ots.value,
-            "kernel_path": path.value}
+            "kernel_path": path.value, "r1": r1.value, "wg_size": wg.value, "col_width": cw.value}
 
 
 def ntt_forward(plan: Plan, data, n_polys: int | None = None, stream=None) -> None:

@@ -10,9 +10,11 @@ supports for that N:
   digit base of 2^8, 2^10 or 2^12 (Section VII);
 * the two-launch path, or the single persistent launch where that shape exists.
 
-Tile shapes (values per lane, workgroup size) are fixed when the library is built, so
-they are not part of the search.  Every candidate's forward transform, inverse and
-negacyclic product are compared bit for bit with those of the default plan on the same
+A second round then takes the fastest few split plans of the first and tries their tile
+shapes: values per lane of the row pass (the per-thread NTT size of Section VI-C: 4 or 8),
+row-pass workgroup lanes (64, 128 or 256) and column-pass tile width (16, 32 or 64 adjacent
+columns), each distinct kernel shape once.  Every candidate's forward transform, inverse
+and negacyclic product are compared bit for bit with those of the default plan on the same
 inputs (all of them compute the same exact residues), and its inverse must undo its
 forward transform; a candidate that fails any of these is dropped and reported.
 
@@ -30,12 +32,13 @@ import time
 from . import (PATH_FUSED, PATH_SPLIT, TWIDDLE_OT, TWIDDLE_TABLE, NttError, ntt_forward, ntt_inverse,
                ntt_plan_create, ntt_plan_get_info, ntt_polymul_negacyclic)
 
-__all__ = ["candidates", "source_hash", "cache_path", "flat_path", "flat_lines", "lookup", "tune",
-           "plan_create_tuned"]
+__all__ = ["candidates", "tile_candidates", "source_hash", "cache_path", "flat_path", "flat_lines", "lookup",
+           "tune", "plan_create_tuned"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 FUSED_SHAPES = {(6, 7), (7, 7), (7, 8), (8, 8), (8, 9)}
 MALL_BYTES = 256 << 20
+TILE_ROUND_PLANS = 3   # split plans of the first round whose tile shapes are tried
 
 
 from .build import source_hash  # noqa: E402  (one definition, compiled into the library)
@@ -71,6 +74,65 @@ def candidates(N: int) -> list[dict]:
     return out
 
 
+COL_LR = 3          # log2 values per lane of the column pass (build-time constant)
+ROW_THREADS = 128   # default row-pass workgroup lanes
+TILE_R1 = (8, 4)
+TILE_WG = (128, 64, 256)
+TILE_COL = (0, 16, 32, 64)
+
+
+def _col_width(logN: int, n1: int, col_width: int) -> int:
+    """Columns per column-pass tile the library takes for a requested width (0 = its
+    automatic choice): at most 1024 lanes of 2^min(3, log2 N1) values each."""
+    t = (1 << n1) >> min(COL_LR, n1)
+    def clip(w):
+        return 1024 // t if w * t > 1024 else w
+    if col_width:
+        return clip(col_width)
+    narrow, wide = clip(16), clip(64)
+    if wide != narrow and wide * t <= 512 and (1 << (logN - n1)) >= wide:
+        return wide
+    return narrow
+
+
+def tile_candidates(N: int, opts: dict) -> list[dict]:
+    """Tile shapes for a split (or one-pass) plan with options `opts`: `opts` plus r1, wg_size
+    and col_width, one per distinct kernel shape, the built-in default (no tile keys) first.
+    Fused and other paths have no tile options."""
+    logN = N.bit_length() - 1
+    if opts.get("kernel_path", PATH_SPLIT) != PATH_SPLIT:
+        return [dict(opts)]
+    n1 = opts.get("log2_n1", 0)
+    if n1 == 0:
+        n1 = 0 if logN <= 12 else logN // 2
+    n1 = max(n1, 0)
+    logm = logN - n1
+    out, seen = [], set()
+    for r1 in TILE_R1:
+        lr = r1.bit_length() - 1
+        t = (1 << logm) >> min(lr, logm)
+        if t > 1024:                      # a row's lanes form one workgroup of at most 1024
+            continue
+        for wg in TILE_WG:
+            v = max(1, wg // t)
+            for cw in (TILE_COL if n1 else (0,)):
+                if cw and (1 << (logN - n1)) < _col_width(logN, n1, cw):
+                    continue
+                shape = (lr, v, _col_width(logN, n1, cw) if n1 else 0)
+                if shape in seen:
+                    continue
+                seen.add(shape)
+                o = dict(opts)
+                if r1 != 8:
+                    o["r1"] = r1
+                if wg != ROW_THREADS:
+                    o["wg_size"] = wg
+                if cw:
+                    o["col_width"] = cw
+                out.append(o)
+    return out
+
+
 def _key(device: str, N: int, primes, polys: int) -> str:
     width = max(int(q).bit_length() for q in primes)
     return f"{device}|{source_hash()}|N={N}|L={len(primes)}|P={polys}|qbits={width}"
@@ -102,7 +164,8 @@ def flat_path(path: str | None = None) -> str:
 
 def flat_lines(cache: dict) -> list[str]:
     """One line per cached shape, in the format of csrc/tune_file.hpp:
-    <device> <source_hash> <N> <L> <P> <qbits> <log2_n1> <twiddle_mode> <ot_stages> <ot_log2_base> <kernel_path>"""
+    <device> <source_hash> <N> <L> <P> <qbits> <log2_n1> <twiddle_mode> <ot_stages> <ot_log2_base> <kernel_path>
+    <r1> <wg_size> <col_width>"""
     out = []
     for key, e in sorted(cache["entries"].items()):
         parts = key.split("|")
@@ -112,7 +175,7 @@ def flat_lines(cache: dict) -> list[str]:
         o = e["opts"]
         vals = [dev, h, n.split("=")[1], l.split("=")[1], p.split("=")[1], qb.split("=")[1],
                 o.get("log2_n1", 0), o.get("twiddle_mode", 0), o.get("ot_stages", 0), o.get("ot_log2_base", 0),
-                o.get("kernel_path", 0)]
+                o.get("kernel_path", 0), o.get("r1", 0), o.get("wg_size", 0), o.get("col_width", 0)]
         out.append(" ".join(str(v) for v in vals))
     return out
 
@@ -220,19 +283,20 @@ def tune(N: int, primes, polys: int = 1, *, steps: int = 100, warmup: int = 3, r
         ref_plan.destroy()
     tried, dropped, refused = [], [], []
     t0 = time.perf_counter()
-    for opts in candidates(N):
+
+    def measure(opts):
         try:
             plan = ntt_plan_create(N, primes, **opts)
         except NttError as e:
             refused.append({"opts": opts, "error": str(e)})
-            continue
+            return
         try:
             bad = _disagrees(torch, plan, x, x2, ref)
             if bad:
                 dropped.append({"opts": opts, "differs": bad})
                 if log:
                     log(f"  N={N} L={len(primes)} P={polys} {opts}: dropped ({bad} differs)")
-                continue
+                return
             us = _time(torch, plan, bufs, steps, warmup)
             info = ntt_plan_get_info(plan)
             tried.append({"opts": opts, "us": round(us, 3), "log2_n1": info["log2_n1"]})
@@ -240,6 +304,14 @@ def tune(N: int, primes, polys: int = 1, *, steps: int = 100, warmup: int = 3, r
                 log(f"  N={N} L={len(primes)} P={polys} {opts}: {us:.1f} us")
         finally:
             plan.destroy()
+
+    for opts in candidates(N):
+        measure(opts)
+    # second round: the tile shapes of the fastest split plans
+    split = sorted((t for t in tried if t["opts"].get("kernel_path", PATH_SPLIT) == PATH_SPLIT), key=lambda t: t["us"])
+    for t in split[:TILE_ROUND_PLANS]:
+        for opts in tile_candidates(N, t["opts"])[1:]:
+            measure(opts)
     if not tried:
         first = refused[0]["error"] if refused else "every candidate disagreed with the first"
         raise RuntimeError(f"no plan options work for N={N}: {first}")

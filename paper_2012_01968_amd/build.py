@@ -20,6 +20,14 @@ SOURCES = ["kernels_fwd_fast.hip", "kernels_inv_fast.hip", "kernels_fwd_wide.hip
            "kernels_mul_fast.hip", "kernels_mul_wide.hip",
            "fused_fwd.hip", "fused_inv.hip", "kernels.hip", "permute.hip", "stages.hip", "kernels32.hip", "crt.hip",
            "capi.cpp"]
+# (object name, source, defines): the row-pass instances, one unit per direction (forward,
+# inverse, key product), arithmetic policy and range of row lengths
+ROW_RANGES = ((1, 7), (8, 10), (11, 13))
+UNITS = [(os.path.splitext(src)[0], src, []) for src in SOURCES] + [
+    (f"rows_{d}_{'fast' if fast else 'wide'}_{lo}_{hi}", "kernels_rows.hip",
+     [f"-DNTTK_ROWS_DIR={d}", f"-DNTTK_ROWS_FAST={'true' if fast else 'false'}", f"-DNTTK_ROWS_LO={lo}",
+      f"-DNTTK_ROWS_HI={hi}"])
+    for d in (0, 1, 2) for fast in (1, 0) for lo, hi in ROW_RANGES]
 ARCH = os.environ.get("NTT_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -49,19 +57,22 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, f'-DNTT_SOURCE_HASH="{source_hash()}"', "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(unit) -> str:
+    name, src, defines = unit
+    obj = os.path.join(BUILD, name + ".o")
+    cmd = [HIPCC, *FLAGS, *defines, f'-DNTT_SOURCE_HASH="{source_hash()}"', "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr[-6000:]}")
+        raise RuntimeError(f"hipcc failed on {name} ({src}):\n{r.stderr[-6000:]}")
     return obj
 
 
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+    # the longest units first, at most one compiler per CPU (each takes a few GB)
+    order = sorted(UNITS, key=lambda u: (u[1] != "kernels_rows.hip", -int(u[2][3].split("=")[1]) if u[2] else 0))
+    with ThreadPoolExecutor(max(1, min(len(order), os.cpu_count() or 1))) as ex:
+        objs = list(ex.map(_compile, order))
     tmp = LIB + f".tmp{os.getpid()}"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)

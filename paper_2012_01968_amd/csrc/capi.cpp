@@ -82,6 +82,8 @@ struct ntt_plan_s {
   int32_t order = NTT_ORDER_BITREV;       // NTT-domain slot order seen by the caller
   int32_t log2_radix = 0;                 // RADIX2 / REGISTER paths: stages per launch
   int32_t word_bits = 64;                 // residue word: 64 (uint64_t) or 32 (uint32_t, q < 2^30)
+  uint32_t row_lr = 0, row_nth = 0, col_w = 0;   // split-pass tile shape (0 = built-in default)
+  uint32_t debug = 0;                     // split-pass debug modes (NTT_DEBUG at creation)
   uint32_t fused_lag = 4;                 // vectors an XCD queue runs pass 1 ahead of pass 2
   uint32_t fused_grid = 1024;             // persistent workgroups (4 per CU)
   uint32_t* d_ctr = nullptr;              // fused-launch counters: 16 + kMaxFusedVectors words
@@ -189,6 +191,10 @@ struct ntt_plan_s {
     a.fast = fast ? 1u : 0u;
     a.mu = d_mu;
     a.bits = d_bits;
+    a.row_lr = row_lr;
+    a.row_nth = row_nth;
+    a.col_w = col_w;
+    a.debug = debug;
     return a;
   }
   int active_ot() const { return twiddle_mode == NTT_TWIDDLE_OT ? ot_stages : 0; }
@@ -244,6 +250,12 @@ static bool apply_tuning(ntt_plan_opts& o, int dev, uint32_t N, const uint64_t* 
   }
   if (!o.log2_n1) o.log2_n1 = e->log2_n1;
   if (!o.kernel_path) o.kernel_path = e->kernel_path;
+  // tile shapes exist for 64-bit plans on the split path
+  if (!o.r1 && !o.wg_size && !o.col_width && o.kernel_path == NTT_PATH_SPLIT && o.word_bits != 32) {
+    o.r1 = e->r1;
+    o.wg_size = e->wg_size;
+    o.col_width = e->col_width;
+  }
   return true;
 }
 
@@ -313,6 +325,28 @@ static ntt_status build_plan(ntt_plan_s* p, uint32_t N, const uint64_t* primes, 
     }
     if (!nttk::shape_supported(p->logN, p->logN1, p->active_ot()))
       return fail(NTT_ERR_UNSUPPORTED, "no kernels for this (N, N1, OT stages) combination");
+  }
+  // ---- debug modes of the split passes: NTT_DEBUG holds any of "poison" (LDS filled with a
+  // poison pattern before use) and "reverse" (workgroups take their tiles in reverse order)
+  if (const char* d = std::getenv("NTT_DEBUG")) {
+    const std::string v = d;
+    if (v.find("poison") != std::string::npos) p->debug |= nttk::kDebugPoisonLds;
+    if (v.find("reverse") != std::string::npos) p->debug |= nttk::kDebugReverseTiles;
+  }
+  // ---- tile shape of the split passes
+  if (o.r1 != 0 && o.r1 != 4 && o.r1 != 8) return fail(NTT_ERR_ARG, "r1 must be 0, 4 or 8");
+  if (o.wg_size != 0 && o.wg_size != 64 && o.wg_size != 128 && o.wg_size != 256)
+    return fail(NTT_ERR_ARG, "wg_size must be 0, 64, 128 or 256");
+  if (o.col_width != 0 && o.col_width != 16 && o.col_width != 32 && o.col_width != 64)
+    return fail(NTT_ERR_ARG, "col_width must be 0, 16, 32 or 64");
+  if (o.r1 || o.wg_size || o.col_width) {
+    if (w32 || stage_path || o.kernel_path == NTT_PATH_FUSED)
+      return fail(NTT_ERR_UNSUPPORTED, "tile options apply to 64-bit plans on the split path");
+    p->row_lr = o.r1 == 4 ? 2u : (o.r1 == 8 ? 3u : 0u);
+    p->row_nth = (uint32_t)o.wg_size;
+    p->col_w = (uint32_t)o.col_width;
+    if (!nttk::tiles_supported(p->logN, p->logN1, p->row_lr, p->row_nth, p->col_w))
+      return fail(NTT_ERR_UNSUPPORTED, "col_width needs a column pass with at least that many columns");
   }
 
   // ---- primes
@@ -974,6 +1008,14 @@ ntt_status ntt_plan_get_info(ntt_plan_t plan, uint32_t* N, uint32_t* L, uint32_t
   if (twiddle_mode) *twiddle_mode = plan->twiddle_mode;
   if (ot_stages) *ot_stages = plan->ot_stages;
   if (kernel_path) *kernel_path = plan->kernel_path;
+  return NTT_OK;
+}
+
+ntt_status ntt_plan_get_tiles(ntt_plan_t plan, int32_t* r1, int32_t* wg_size, int32_t* col_width) {
+  if (ntt_status s = check_plan(plan)) return s;
+  if (r1) *r1 = (int32_t)plan->row_lr ? (1 << plan->row_lr) : 0;
+  if (wg_size) *wg_size = (int32_t)plan->row_nth;
+  if (col_width) *col_width = (int32_t)plan->col_w;
   return NTT_OK;
 }
 

@@ -12,6 +12,11 @@ struct VecDesc;
 // Whether a (log2 N, log2 N1, OT stages) combination has kernels built in.
 bool shape_supported(uint32_t logN, uint32_t logN1, int ot_stages);
 
+// Whether a tile shape of the split passes has kernels built in and fits the split: row pass
+// log2 values per lane (0 = default, 2, 3) and workgroup lanes (0 = default, 64, 128, 256);
+// column pass width (0 = automatic, 16, 32, 64 adjacent columns, at most N2).
+bool tiles_supported(uint32_t logN, uint32_t logN1, uint32_t row_lr, uint32_t row_nth, uint32_t col_w);
+
 // Forward / inverse transform of every vector described by `a`, enqueued on `st`.
 hipError_t launch_forward(const PassArgs& a, int ot_stages, hipStream_t st);
 hipError_t launch_inverse(const PassArgs& a, int ot_stages, hipStream_t st);

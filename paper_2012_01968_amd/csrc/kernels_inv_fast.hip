@@ -2,5 +2,9 @@
 #include "kernels_impl.hpp"
 
 namespace nttk {
+// row passes: instantiated in kernels_rows.hip
+#define X(LM) NTTK_INV_ROWS(extern, true, LM)
+NTTK_ROW_CASES(X)
+#undef X
 template hipError_t inverse_pass<true>(const PassArgs&, int, int, hipStream_t);
 }  // namespace nttk

@@ -58,7 +58,18 @@ struct PassArgs {
   // Loaded rather than derived from q in the kernel, so that the compiler adds them as
   // 64-bit operands instead of re-deriving them from q's halves.
   const uint64_t* mc;
+  // Tile shape of the split passes (0 = the built-in default): row pass values per lane as
+  // log2 (2 or 3) and workgroup lanes (64, 128 or 256); column pass width in adjacent
+  // columns (16, 32 or 64).
+  uint32_t row_lr;
+  uint32_t row_nth;
+  uint32_t col_w;
+  // Debug modes of the split passes (kDebug* bits, 0 in normal use).
+  uint32_t debug;
 };
+
+constexpr uint32_t kDebugPoisonLds = 1;      // poison LDS before use
+constexpr uint32_t kDebugReverseTiles = 2;   // reverse the workgroup -> tile mapping
 
 // Base address and limb of vector `vec` of a launch: dense [P][L][N] batches place vector
 // p*L + l at data + (p*L + l)*N with prime l; list launches read both from the list.

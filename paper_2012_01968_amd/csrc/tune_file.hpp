@@ -4,10 +4,12 @@
 // one line per tuned shape and no comments:
 //
 //   <device> <source_hash> <N> <L> <P> <qbits> <log2_n1> <twiddle_mode> <ot_stages> <ot_log2_base> <kernel_path>
+//       [<r1> <wg_size> <col_width>]
 //
 // device is "<arch>:<CUs>CU" (e.g. gfx950:256CU), source_hash the hash of the kernel sources
 // the choice was measured with, P the polynomials per call and qbits the width of the largest
-// prime.  A line that does not parse is skipped.
+// prime; the three tile fields (values per lane and workgroup lanes of the row pass, column
+// tile width; 0 = default) are optional.  A line that does not parse is skipped.
 #pragma once
 #include <cmath>
 #include <cstdint>
@@ -21,6 +23,7 @@ struct TuneEntry {
   std::string device, hash;
   uint32_t N = 0, L = 0, P = 0, qbits = 0;
   int32_t log2_n1 = 0, twiddle_mode = 0, ot_stages = 0, ot_log2_base = 0, kernel_path = 0;
+  int32_t r1 = 0, wg_size = 0, col_width = 0;
 };
 
 inline std::vector<TuneEntry> parse_tune_file(const std::string& text) {
@@ -30,11 +33,20 @@ inline std::vector<TuneEntry> parse_tune_file(const std::string& text) {
   while (std::getline(lines, line)) {
     std::istringstream f(line);
     TuneEntry e;
-    std::string extra;
-    if (f >> e.device >> e.hash >> e.N >> e.L >> e.P >> e.qbits >> e.log2_n1 >> e.twiddle_mode >> e.ot_stages >>
-            e.ot_log2_base >> e.kernel_path &&
-        !(f >> extra))
-      out.push_back(e);
+    if (!(f >> e.device >> e.hash >> e.N >> e.L >> e.P >> e.qbits >> e.log2_n1 >> e.twiddle_mode >> e.ot_stages >>
+          e.ot_log2_base >> e.kernel_path))
+      continue;
+    std::vector<std::string> rest;
+    std::string tok;
+    while (f >> tok) rest.push_back(tok);
+    if (rest.size() == 3) {
+      std::istringstream t(rest[0] + " " + rest[1] + " " + rest[2]);
+      std::string extra;
+      if (!(t >> e.r1 >> e.wg_size >> e.col_width) || (t >> extra)) continue;
+    } else if (!rest.empty()) {
+      continue;
+    }
+    out.push_back(e);
   }
   return out;
 }

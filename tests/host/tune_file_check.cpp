@@ -21,10 +21,17 @@ int main() {
       "gfx950:256CU abc 65536 45 2 62 9 1 0 10 1\n"        // other prime width
       "gfx950:256CU abc 131072 60 2 60 6 1 0 10 1\n"
       "gfx950:256CU abc 65536 45 2 60 6 2 1\n"             // truncated: skipped
-      "gfx950:256CU abc 65536 45 2 60 6 2 1 10 1 extra\n"  // trailing field: skipped
+      "gfx950:256CU abc 65536 45 2 60 6 2 1 10 1 extra\n"  // one trailing field: skipped
+      "gfx950:256CU abc 16384 8 4 60 5 1 0 10 1 4 256 32\n"   // with the tile fields
+      "gfx950:256CU abc 16384 8 4 61 5 1 0 10 1 4 256\n"      // two tile fields: skipped
+      "gfx950:256CU abc 16384 8 4 62 5 1 0 10 1 4 x 32\n"     // non-numeric tile field: skipped
       "garbage\n";
   const auto es = nttt::parse_tune_file(text);
-  check(es.size() == 7, "seven well-formed lines");
+  check(es.size() == 8, "eight well-formed lines");
+  const nttt::TuneEntry* t = nttt::pick_tune_entry(es, "gfx950:256CU", "abc", 16384, 8, 4, 60);
+  check(t && t->r1 == 4 && t->wg_size == 256 && t->col_width == 32 && t->log2_n1 == 5, "tile fields");
+  t = nttt::pick_tune_entry(es, "gfx950:256CU", "abc", 65536, 45, 2, 60);
+  check(t && t->r1 == 0 && t->wg_size == 0 && t->col_width == 0, "tile fields default to zero");
   const nttt::TuneEntry* e = nttt::pick_tune_entry(es, "gfx950:256CU", "abc", 65536, 45, 2, 60);
   check(e && e->log2_n1 == 6 && e->twiddle_mode == 2 && e->ot_stages == 1 && e->ot_log2_base == 10 &&
             e->kernel_path == 1,

@@ -39,6 +39,41 @@ def test_candidates_follow_the_shape_rules():
             at.candidates(bad)
 
 
+def test_tile_candidates_are_distinct_kernel_shapes():
+    """The second tuning round's tile shapes: the default first, every r1 / wg_size / col_width
+    value one the library accepts, and no two candidates that launch the same kernel shape
+    (same values per lane, rows per workgroup and effective column width)."""
+    for logN in range(1, 18):
+        N = 1 << logN
+        for opts in at.candidates(N):
+            tiles = at.tile_candidates(N, opts)
+            assert tiles[0] == opts
+            if opts["kernel_path"] == PATH_FUSED:
+                assert tiles == [opts]
+                continue
+            n1 = opts["log2_n1"] if opts["log2_n1"] > 0 else 0
+            logm = logN - n1
+            shapes = set()
+            for t in tiles:
+                assert {k: v for k, v in t.items() if k not in ("r1", "wg_size", "col_width")} == opts
+                r1, wg, cw = t.get("r1", 8), t.get("wg_size", 128), t.get("col_width", 0)
+                assert r1 in (4, 8) and wg in (64, 128, 256) and cw in (0, 16, 32, 64)
+                if n1 == 0:
+                    assert cw == 0
+                lr = r1.bit_length() - 1
+                rows_t = (1 << logm) >> min(lr, logm)
+                assert rows_t <= 1024
+                w = at._col_width(logN, n1, cw) if n1 else 0
+                if cw:
+                    assert (1 << (logN - n1)) >= w
+                shapes.add((lr, max(1, wg // rows_t), w))
+            assert len(shapes) == len(tiles)
+    # N = 2^16, N1 = 64: 1024-point rows (128 lanes at r1 = 8, 256 at r1 = 4), 64-point columns
+    t16 = at.tile_candidates(1 << 16, dict(log2_n1=6, kernel_path=PATH_SPLIT, twiddle_mode=TWIDDLE_TABLE))
+    assert {(t.get("r1", 8), t.get("wg_size", 128)) for t in t16} == {(8, 128), (8, 256), (4, 128)}
+    assert at._col_width(16, 6, 0) == 64 and at._col_width(16, 6, 16) == 16 and at._col_width(16, 10, 64) == 8
+
+
 def test_cache_round_trip(tmp_path):
     p = str(tmp_path / "cache.json")
     assert at._load(p) == {"version": 1, "entries": {}}

@@ -33,8 +33,10 @@ def test_committed_traffic_covers_its_configuration():
     assert keys
     for k in keys:
         assert b.read_traffic(k, h) > 0
-    # the plans that win the headline measurement on some box carry instruction counts as well
-    for plan in ("table-split-n1=6", "table-split-n1=8", "ot1-split-n1=6"):
+    # the plans that win the headline measurement on some box (the default split and the tuner's)
+    # carry bytes and instruction counts for all four passes
+    plans = {k.split(":")[0] for k in keys} | {"table-split-n1=6", "table-split-n1=8"}
+    for plan in plans:
         for kern in ("fwd_col", "fwd_row", "inv_row", "inv_col"):
             assert b.read_traffic(f"{plan}:{kern}", h) > 0
             assert b.read_traffic(f"{plan}:{kern}", h, field="valu_insts_per_launch") > 0
@@ -44,3 +46,5 @@ def test_plan_names():
     b = load_bench()
     assert b.variant_key({"kernel_path": 1, "log2_n1": 8}, 0) == "table-split-n1=8"
     assert b.variant_key({"kernel_path": 2, "log2_n1": 7}, 2) == "ot2-fused-n1=7"
+    assert b.variant_key({"kernel_path": 1, "log2_n1": 6, "r1": 4, "wg_size": 0, "col_width": 32}, 1) == \
+        "ot1-split-n1=6-r1=4-col_width=32"

@@ -10,12 +10,30 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2012_01968_amd", "csrc")
 
 
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
+
+
+@pytest.mark.parametrize("sanitize", [False, True], ids=["plain", "asan_ubsan"])
 @pytest.mark.parametrize("check", ["plan_life_check", "tune_file_check", "crt_math_check"])
-def test_host_check(tmp_path, check):
+def test_host_check(tmp_path, check, sanitize):
+    """Also built with AddressSanitizer and UndefinedBehaviorSanitizer: the headers are the
+    library's own host code (reference counts, the tuner file reader, the conversion tables)."""
     exe = tmp_path / check
-    subprocess.check_call(["g++", "-std=c++17", "-O2", "-Wall", "-I", CSRC,
-                           os.path.join(ROOT, "tests", "host", check + ".cpp"), "-o", str(exe)])
-    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    subprocess.check_call(["g++", "-std=c++17", "-O1" if sanitize else "-O2", "-Wall", *(SANITIZE if sanitize else []),
+                           "-I", CSRC, os.path.join(ROOT, "tests", "host", check + ".cpp"), "-o", str(exe)])
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "0 failures" in out.stdout
+
+
+def test_oracle_under_sanitizers(tmp_path):
+    """The C oracle under AddressSanitizer and UndefinedBehaviorSanitizer, every entry point on
+    N = 2..256, results checked against each other (tests/host/oracle_sanitize_check.c)."""
+    exe = tmp_path / "oracle_sanitize_check"
+    subprocess.check_call(["gcc", "-std=c11", "-O1", "-Wall", *SANITIZE,
+                           os.path.join(ROOT, "tests", "host", "oracle_sanitize_check.c"),
+                           os.path.join(ROOT, "oracle", "ntt_oracle.c"), "-o", str(exe)])
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stdout + out.stderr
     assert "0 failures" in out.stdout
 
@@ -34,5 +52,5 @@ def test_flat_tune_file_matches_the_json_cache():
         assert f.read().splitlines() == lines
     for line in lines:
         fields = line.split()
-        assert len(fields) == 11
+        assert len(fields) == 14
         assert all(x.lstrip("-").isdigit() for x in fields[2:])

@@ -53,7 +53,8 @@ class _Opts(ctypes.Structure):
                 ("ot_log2_base", ctypes.c_int32), ("log2_n1", ctypes.c_int32),
                 ("kernel_path", ctypes.c_int32), ("use_autotune", ctypes.c_int32),
                 ("tune_polys", ctypes.c_int32), ("order", ctypes.c_int32), ("log2_radix", ctypes.c_int32),
-                ("word_bits", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("word_bits", ctypes.c_int32), ("r1", ctypes.c_int32), ("wg_size", ctypes.c_int32),
+                ("col_width", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 def _create(lib, N, primes, opts=None):
@@ -106,6 +107,18 @@ def test_argument_errors_are_synchronous(lib):
     assert _create(lib, 1 << 16, [q], o) == (-6, None)             # radix-2 path: table twiddles only
     o = _Opts(0, 0, 0, 9, 2)
     assert _create(lib, 1 << 16, [q], o) == (-6, None)             # no fused 2^9 x 2^7 shape
+    o = _Opts(0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 2)
+    assert _create(lib, 1 << 16, [q], o) == (-1, None)             # r1 is 4 or 8
+    o = _Opts(0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 96)
+    assert _create(lib, 1 << 16, [q], o) == (-1, None)             # wg_size is 64, 128 or 256
+    o = _Opts(0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 128)
+    assert _create(lib, 1 << 16, [q], o) == (-1, None)             # col_width is 16, 32 or 64
+    o = _Opts(0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 16)
+    assert _create(lib, 1 << 10, [q], o) == (-6, None)             # one-pass plan: no column tile
+    o = _Opts(0, 0, 0, 0, 3, 0, 0, 0, 0, 0, 4)
+    assert _create(lib, 1 << 16, [q], o) == (-6, None)             # tiles belong to the split path
+    o = _Opts(0, 0, 0, 0, 0, 0, 0, 0, 0, 32, 4)
+    assert _create(lib, 1 << 16, [(1 << 29) + 1], o) == (-6, None) # and to 64-bit plans
     lib.ntt_forward.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p]
     lib.ntt_forward.restype = ctypes.c_int
     assert lib.ntt_forward(None, None, 1, None) == -1

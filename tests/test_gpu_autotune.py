@@ -23,7 +23,12 @@ def test_tune_caches_and_matches_oracle(tmp_path, logN, L, P):
     primes = synth.gen_primes(3000 + logN, N, 60, L)
     path = str(tmp_path / "tune.json")
     e = autotune.tune(N, primes, P, steps=2, warmup=1, path=path)
-    assert e["dropped"] == [] and len(e["tried"]) == len(autotune.candidates(N))
+    # every first-round candidate, then the tile shapes of the fastest split plans
+    first = autotune.candidates(N)
+    assert e["dropped"] == [] and len(e["tried"]) > len(first)
+    tried = [t["opts"] for t in e["tried"]]
+    assert all(c in tried for c in first)
+    assert any("r1" in o or "wg_size" in o or "col_width" in o for o in tried)
     assert e["us"] == min(t["us"] for t in e["tried"])
     assert autotune.tune(N, primes, P, path=path) == e                # served from the cache
     plan = autotune.plan_create_tuned(N, primes, P, path=path)

@@ -84,3 +84,89 @@ def test_every_candidate_plan(logN, bits):
     # at 60 bits the sweep must reach every candidate
     if bits == 60:
         assert not refused
+
+
+@pytest.mark.parametrize("logN", list(range(1, 18)))
+def test_every_tile_shape(logN):
+    """Every tile shape the tuner's second round can choose (values per lane and workgroup
+    lanes of the row pass, column tile width), on every split of N and with table, one-stage
+    and two-stage OT twiddles (60-bit primes): forward, inverse and negacyclic product against
+    the oracle.  Together these reach every row, key-product and column kernel instance that
+    a tile option selects."""
+    N = 1 << logN
+    seed = 5000 + logN
+    primes = synth.gen_primes(seed, N, 60, L)
+    psis = oracle.roots(primes, N)
+    a = synth.residue_batch(seed, primes, N, P)
+    b = synth.residue_batch(seed + 1, primes, N, P)
+    b[1, 2, :] = np.uint64(primes[2] - 1)
+    want_f = oracle.forward(a, primes, psis, THREADS)
+    want_i = oracle.inverse(a, primes, psis, THREADS)
+    want_m = oracle.polymul(a, b, primes, psis, THREADS)
+    da, db = dev(a), dev(b)
+    checked = 0
+    bases = [c for c in autotune.candidates(N) if c["kernel_path"] == ntt.PATH_SPLIT and
+             (c["twiddle_mode"] == ntt.TWIDDLE_TABLE or c.get("ot_log2_base") == min(10, logN - 1))]
+    for base in bases:
+        for opts in autotune.tile_candidates(N, base)[1:]:
+            plan = ntt.ntt_plan_create(N, primes, **opts)
+            try:
+                info = ntt.ntt_plan_get_info(plan)
+                assert (info["r1"], info["wg_size"], info["col_width"]) == \
+                    (opts.get("r1", 0), opts.get("wg_size", 0), opts.get("col_width", 0))
+                d = da.clone()
+                ntt.ntt_forward(plan, d)
+                torch.cuda.synchronize()
+                assert np.array_equal(host(d), want_f), f"N=2^{logN} {opts}: forward"
+                ntt.ntt_inverse(plan, d)
+                torch.cuda.synchronize()
+                assert np.array_equal(host(d), a), f"N=2^{logN} {opts}: inverse(forward)"
+                d = da.clone()
+                ntt.ntt_inverse(plan, d)
+                torch.cuda.synchronize()
+                assert np.array_equal(host(d), want_i), f"N=2^{logN} {opts}: inverse"
+                c = torch.empty_like(da)
+                ntt.ntt_polymul_negacyclic(plan, da, db, c)
+                torch.cuda.synchronize()
+                assert np.array_equal(host(c), want_m), f"N=2^{logN} {opts}: product"
+                checked += 1
+            finally:
+                plan.destroy()
+    assert checked > 0
+
+
+@pytest.mark.parametrize("mode", ["poison", "reverse", "poison,reverse"])
+def test_debug_modes_change_nothing(mode, monkeypatch):
+    """With the split passes' LDS poisoned before use and with their workgroups taking tiles
+    in reverse order, every split and tile shape at N = 2^10, 2^13 and 2^16 still matches the
+    oracle: no exchange reads a slot it did not write and no tile depends on another."""
+    monkeypatch.setenv("NTT_DEBUG", mode)
+    for logN in (10, 13, 16):
+        N = 1 << logN
+        seed = 6000 + logN
+        primes = synth.gen_primes(seed, N, 60, L)
+        psis = oracle.roots(primes, N)
+        a = synth.residue_batch(seed, primes, N, P)
+        b = synth.residue_batch(seed + 1, primes, N, P)
+        want_f = oracle.forward(a, primes, psis, THREADS)
+        want_m = oracle.polymul(a, b, primes, psis, THREADS)
+        da, db = dev(a), dev(b)
+        for base in autotune.candidates(N):
+            if base["kernel_path"] != ntt.PATH_SPLIT or base.get("ot_log2_base", 10) != 10:
+                continue
+            for opts in autotune.tile_candidates(N, base):
+                plan = ntt.ntt_plan_create(N, primes, **opts)
+                try:
+                    d = da.clone()
+                    ntt.ntt_forward(plan, d)
+                    torch.cuda.synchronize()
+                    assert np.array_equal(host(d), want_f), f"{mode} N=2^{logN} {opts}: forward"
+                    ntt.ntt_inverse(plan, d)
+                    torch.cuda.synchronize()
+                    assert np.array_equal(host(d), a), f"{mode} N=2^{logN} {opts}: inverse(forward)"
+                    c = torch.empty_like(da)
+                    ntt.ntt_polymul_negacyclic(plan, da, db, c)
+                    torch.cuda.synchronize()
+                    assert np.array_equal(host(c), want_m), f"{mode} N=2^{logN} {opts}: product"
+                finally:
+                    plan.destroy()
