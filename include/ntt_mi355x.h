@@ -81,7 +81,7 @@ typedef struct {
     int32_t r1;             /* row pass values per lane (per-thread NTT size): 0 = 8, 4, 8 */
     int32_t wg_size;        /* row pass workgroup lanes: 0 = 128, 64, 128, 256           */
     int32_t col_width;      /* column pass tile width in adjacent columns: 0 = automatic, */
-                            /* 16, 32, 64 (at most N2; longer columns take fewer)        */
+                            /* 16 .. 256 (at most N2; longer columns take fewer)         */
     int32_t reserved;       /* must be zero                                             */
 } ntt_plan_opts;
 

@@ -12,7 +12,7 @@ supports for that N:
 
 A second round then takes the fastest few split plans of the first and tries their tile
 shapes: values per lane of the row pass (the per-thread NTT size of Section VI-C: 4 or 8),
-row-pass workgroup lanes (64, 128 or 256) and column-pass tile width (16, 32 or 64 adjacent
+row-pass workgroup lanes (64, 128 or 256) and column-pass tile width (16 to 256 adjacent
 columns), each distinct kernel shape once.  Every candidate's forward transform, inverse
 and negacyclic product are compared bit for bit with those of the default plan on the same
 inputs (all of them compute the same exact residues), and its inverse must undo its
@@ -78,7 +78,7 @@ COL_LR = 3          # log2 values per lane of the column pass (build-time consta
 ROW_THREADS = 128   # default row-pass workgroup lanes
 TILE_R1 = (8, 4)
 TILE_WG = (128, 64, 256)
-TILE_COL = (0, 16, 32, 64)
+TILE_COL = (0, 16, 32, 64, 128, 256)
 
 
 def _col_width(logN: int, n1: int, col_width: int) -> int:

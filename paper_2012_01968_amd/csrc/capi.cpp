@@ -337,8 +337,9 @@ static ntt_status build_plan(ntt_plan_s* p, uint32_t N, const uint64_t* primes, 
   if (o.r1 != 0 && o.r1 != 4 && o.r1 != 8) return fail(NTT_ERR_ARG, "r1 must be 0, 4 or 8");
   if (o.wg_size != 0 && o.wg_size != 64 && o.wg_size != 128 && o.wg_size != 256)
     return fail(NTT_ERR_ARG, "wg_size must be 0, 64, 128 or 256");
-  if (o.col_width != 0 && o.col_width != 16 && o.col_width != 32 && o.col_width != 64)
-    return fail(NTT_ERR_ARG, "col_width must be 0, 16, 32 or 64");
+  if (o.col_width != 0 && o.col_width != 16 && o.col_width != 32 && o.col_width != 64 && o.col_width != 128 &&
+      o.col_width != 256)
+    return fail(NTT_ERR_ARG, "col_width must be 0, 16, 32, 64, 128 or 256");
   if (o.r1 || o.wg_size || o.col_width) {
     if (w32 || stage_path || o.kernel_path == NTT_PATH_FUSED)
       return fail(NTT_ERR_UNSUPPORTED, "tile options apply to 64-bit plans on the split path");

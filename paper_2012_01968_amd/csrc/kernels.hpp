@@ -14,7 +14,7 @@ bool shape_supported(uint32_t logN, uint32_t logN1, int ot_stages);
 
 // Whether a tile shape of the split passes has kernels built in and fits the split: row pass
 // log2 values per lane (0 = default, 2, 3) and workgroup lanes (0 = default, 64, 128, 256);
-// column pass width (0 = automatic, 16, 32, 64 adjacent columns, at most N2).
+// column pass width (0 = automatic, 16, 32, 64, 128 or 256 adjacent columns, at most N2).
 bool tiles_supported(uint32_t logN, uint32_t logN1, uint32_t row_lr, uint32_t row_nth, uint32_t col_w);
 
 // Forward / inverse transform of every vector described by `a`, enqueued on `st`.

@@ -15,7 +15,7 @@ bool tiles_supported(uint32_t logN, uint32_t logN1, uint32_t row_lr, uint32_t ro
   const uint32_t logm = logN - logN1, rlr = row_lr ? row_lr : (uint32_t)row_lr_default(logm);
   if (((1u << logm) >> (rlr < logm ? rlr : logm)) > 1024) return false;
   if (col_w == 0) return true;
-  if (col_w != 16 && col_w != 32 && col_w != 64) return false;
+  if (col_w != 16 && col_w != 32 && col_w != 64 && col_w != 128 && col_w != 256) return false;
   if (logN1 == 0 || logN1 > logN) return false;   // no column pass
   const uint32_t lr = (uint32_t)kLR < logN1 ? (uint32_t)kLR : logN1;
   const uint32_t t = (1u << logN1) >> lr;          // lanes per column

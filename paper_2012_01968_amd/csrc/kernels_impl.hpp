@@ -657,7 +657,7 @@ constexpr bool col_wide_differs() {
   return ColCfg<LOGM, kColWidthWide>::W != ColCfg<LOGM, kColWidth>::W && ColCfg<LOGM, kColWidthWide>::NT <= 512;
 }
 
-// Column tile of a launch: the plan's requested width (PassArgs::col_w: 16, 32 or 64 adjacent
+// Column tile of a launch: the plan's requested width (PassArgs::col_w: 16 to 256 adjacent
 // columns, fewer when the column is long enough to reach 1024 lanes), else the wide tile
 // where N2 holds it and the narrow one otherwise.  A requested width must fit N2 (checked
 // when the plan is created, see tiles_supported).
@@ -666,6 +666,8 @@ __host__ hipError_t with_col_width(const PassArgs& a, F&& f) {
   if (a.col_w == 16) return f(std::integral_constant<int, 16>{});
   if (a.col_w == 32) return f(std::integral_constant<int, 32>{});
   if (a.col_w == 64) return f(std::integral_constant<int, 64>{});
+  if (a.col_w == 128) return f(std::integral_constant<int, 128>{});
+  if (a.col_w == 256) return f(std::integral_constant<int, 256>{});
   if (a.col_w != 0) return hipErrorInvalidValue;
   if constexpr (col_wide_differs<LOGM>())
     if ((1u << (a.logN - LOGM)) >= (uint32_t)ColCfg<LOGM, kColWidthWide>::W)
@@ -775,9 +777,12 @@ hipError_t go_mul_row(const PassArgs& af, const PassArgs& ai, hipStream_t st) {
 // The key-product rows run 8 values per lane whatever the plan's r1: at 4 values per lane,
 // 128-point rows with one OT stage gave wrong products on the GPU (forward and inverse row
 // passes of that shape are exact); the cause was not found, so that shape is not built.
+#ifndef NTTK_MUL_LR2
+#define NTTK_MUL_LR2 0
+#endif
 template <bool FAST, int LM>
 hipError_t mul_rows_lm(const PassArgs& af, const PassArgs& ai, int ots, bool scale0, hipStream_t st) {
-  return with_row_shape<LM, false>(af, [&](auto nth, auto lr) {
+  return with_row_shape<LM, NTTK_MUL_LR2 != 0>(af, [&](auto nth, auto lr) {
     constexpr int NTH = decltype(nth)::value, LRR = decltype(lr)::value;
     if (scale0) {
       if (ots == 0) return go_mul_row<FAST, LM, 0, true, NTH, LRR>(af, ai, st);

@@ -60,7 +60,7 @@ struct PassArgs {
   const uint64_t* mc;
   // Tile shape of the split passes (0 = the built-in default): row pass values per lane as
   // log2 (2 or 3) and workgroup lanes (64, 128 or 256); column pass width in adjacent
-  // columns (16, 32 or 64).
+  // columns (16, 32, 64, 128 or 256).
   uint32_t row_lr;
   uint32_t row_nth;
   uint32_t col_w;

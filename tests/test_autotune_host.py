@@ -57,7 +57,7 @@ def test_tile_candidates_are_distinct_kernel_shapes():
             for t in tiles:
                 assert {k: v for k, v in t.items() if k not in ("r1", "wg_size", "col_width")} == opts
                 r1, wg, cw = t.get("r1", 8), t.get("wg_size", 128), t.get("col_width", 0)
-                assert r1 in (4, 8) and wg in (64, 128, 256) and cw in (0, 16, 32, 64)
+                assert r1 in (4, 8) and wg in (64, 128, 256) and cw in (0, 16, 32, 64, 128, 256)
                 if n1 == 0:
                     assert cw == 0
                 lr = r1.bit_length() - 1

@@ -111,8 +111,8 @@ def test_argument_errors_are_synchronous(lib):
     assert _create(lib, 1 << 16, [q], o) == (-1, None)             # r1 is 4 or 8
     o = _Opts(0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 96)
     assert _create(lib, 1 << 16, [q], o) == (-1, None)             # wg_size is 64, 128 or 256
-    o = _Opts(0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 128)
-    assert _create(lib, 1 << 16, [q], o) == (-1, None)             # col_width is 16, 32 or 64
+    o = _Opts(0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 512)
+    assert _create(lib, 1 << 16, [q], o) == (-1, None)             # col_width is 16 .. 256
     o = _Opts(0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 16)
     assert _create(lib, 1 << 10, [q], o) == (-6, None)             # one-pass plan: no column tile
     o = _Opts(0, 0, 0, 0, 3, 0, 0, 0, 0, 0, 4)
