@@ -8,7 +8,10 @@ forward NTT of the whole ciphertext followed by its inverse, i.e. 180 limb-NTTs.
 Inputs are resident in HBM before timing starts.  The step rotates through copies of
 the ciphertext totalling more than the 256 MB Infinity Cache, so every step reads its
 input from HBM.  Forward then inverse returns each buffer to its original content, so
-the copies stay valid for the whole run.
+the copies stay valid for the whole run.  Steps are independent and are issued round-robin
+over --streams streams (2 by default; copy j always on stream j mod S), so that one step's
+kernels fill the tail of the other stream's; the same steps on one stream are reported
+beside them.
 
 Printed (stdout, one JSON line): limb-NTTs/s over the timed steps, the roofline of the
 dominant kernel (algorithmic bytes of one launch / its average duration from HIP events
@@ -140,6 +143,9 @@ def main() -> int:
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the plan tuner: named variants only, default plans in the other sections")
     ap.add_argument("--log2-n1", type=int, default=0)
+    ap.add_argument("--streams", type=int, default=2,
+                    help="streams the timed steps are issued on, round-robin (1 = every step on one stream); "
+                         "steps are independent, so steps on different streams overlap on the GPU")
     ap.add_argument("--rotate-gib", type=float, default=1.25, help="total size of the rotating input copies")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--serve-seconds", type=float, default=30.0,
@@ -175,6 +181,9 @@ def main() -> int:
     host = synth.residue_batch(WORKLOAD["seed"], primes, N, P)
     ct_bytes = host.nbytes
     R = max(2, int(np.ceil(args.rotate_gib * 2**30 / ct_bytes)))
+    n_streams = max(1, args.streams)
+    R = -(-R // n_streams) * n_streams    # a multiple of the stream count: copy j stays on one stream
+    streams = [torch.cuda.Stream() for _ in range(n_streams)] if n_streams > 1 else []
     dev0 = torch.from_numpy(host.view(np.int64)).to("cuda")
     bufs = torch.empty((R,) + tuple(dev0.shape), dtype=torch.int64, device="cuda")
     bufs[:] = dev0
@@ -236,34 +245,58 @@ def main() -> int:
         npass = ntt.ntt_plan_num_passes(plan)
         fused = info["kernel_path"] == ntt.PATH_FUSED
 
-        def step(i):
-            b = bufs[i % R]
-            ntt.ntt_forward(plan, b)
-            ntt.ntt_inverse(plan, b)
+        def timed_steps(S: int):
+            """Time args.steps steps issued round-robin over S streams (step i on stream i mod S,
+            so copy j is always on stream j mod S); returns (ms per step, wall s, per-step ms)."""
+            sts = streams[:S] if S > 1 else [torch.cuda.current_stream()]
 
-        ramp(step, args.ramp_ms)
-        for i in range(args.warmup):
-            step(i)
-        torch.cuda.synchronize()
-        # the timed steps: events only around the whole run (an event between steps makes the
-        # queue drain before the next kernel starts, which would be timed as well)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        e0.record()
-        for i in range(args.steps):
-            step(args.warmup + i)
-        e1.record()
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        ms = e0.elapsed_time(e1) / args.steps
-        # per-step latency distribution: a second pass with an event after every step
-        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-        evs[0].record()
-        for i in range(args.steps):
-            step(i)
-            evs[i + 1].record()
-        torch.cuda.synchronize()
-        per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
+            def step(i):
+                b = bufs[i % R]
+                ntt.ntt_forward(plan, b, None, sts[i % S])
+                ntt.ntt_inverse(plan, b, None, sts[i % S])
+
+            ramp(step, args.ramp_ms)
+            for i in range(args.warmup):
+                step(i)
+            torch.cuda.synchronize()
+            # the timed steps: events only around the whole run (an event between steps makes the
+            # queue drain before the next kernel starts, which would be timed as well); with several
+            # streams they wait for the start event and the end event waits for all of them
+            main_st = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            e0.record(main_st)
+            if S > 1:
+                for st in sts:
+                    st.wait_event(e0)
+            for i in range(args.steps):
+                step(args.warmup + i)
+            if S > 1:
+                for st in sts:
+                    done = torch.cuda.Event()
+                    done.record(st)
+                    main_st.wait_event(done)
+            e1.record(main_st)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            ms = e0.elapsed_time(e1) / args.steps
+            # per-step latency: a second pass with events around every step on its own stream (the
+            # start event completes when the stream reaches the step, so this is the step's time
+            # from its start to its end, sharing the GPU with the other streams' steps)
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(args.steps)]
+            for i in range(args.steps):
+                evs[i][0].record(sts[i % S])
+                step(i)
+                evs[i][1].record(sts[i % S])
+            torch.cuda.synchronize()
+            per = np.array([a.elapsed_time(b) for a, b in evs])
+            return ms, wall, per
+
+        ms, wall, per = timed_steps(n_streams)
+        ms1 = ms
+        if n_streams > 1:
+            ms1, _, _ = timed_steps(1)
 
         # per-kernel durations: each kernel launched back to back over K distinct rotating copies,
         # with events only around each run of K launches (an event between two kernels drains the
@@ -312,9 +345,10 @@ def main() -> int:
         plain_ms = pe0.elapsed_time(pe1) / args.steps
 
         ok = bool(torch.equal(bufs[0], dev0) and torch.equal(bufs[R - 1], dev0))
-        results[mode] = dict(plan=plan, info=info, npass=npass, ms=ms, per=per, wall=wall, kms=kms,
+        results[mode] = dict(plan=plan, info=info, npass=npass, ms=ms, ms1=ms1, per=per, wall=wall, kms=kms,
                              plain_ms=plain_ms, roundtrip_ok=ok)
-        log(f"[{mode}] {ms*1e3:.1f} us/step  ({180/ms*1e3/1e6:.3f} M NTTs/s)  kernels(us): "
+        log(f"[{mode}] {ms*1e3:.1f} us/step over {n_streams} streams, {ms1*1e3:.1f} on one  "
+            f"({180/ms*1e3/1e6:.3f} M NTTs/s)  kernels(us): "
             + ", ".join(f"{k}={v*1e3:.1f}" for k, v in kms.items())
             + f"  plain {plain_ms*1e3:.1f} us/step  roundtrip_ok={ok}")
 
@@ -361,7 +395,7 @@ def main() -> int:
     torch.cuda.empty_cache()
     polymul = None if args.no_polymul else polymul_bench(args)
     ablation = None if args.no_ablation else ablation_bench(args)
-    word32 = None if args.no_word32 else word32_bench(args, r["ms"])
+    word32 = None if args.no_word32 else word32_bench(args, r["ms1"])   # both on one stream
     crt = None if args.no_crt else crt_bench(args)
     uneven = None if args.no_uneven else uneven_batch_bench(args)
     serving = serve_bench(args) if args.serve_seconds > 0 else None
@@ -374,7 +408,8 @@ def main() -> int:
         "config": {"workload": "one ciphertext, N=2^16, L=45 primes in [2^59,2^60) (seed 2), 2 polys, "
                                "forward NTT then inverse NTT (180 limb-NTTs per step)",
                    "N": N, "L": L, "polys": P, "variant": best, "plan": variant_key(info, ots),
-                   "ot_stages": ots, "log2_n1": info["log2_n1"], "rotating_copies": R},
+                   "ot_stages": ots, "log2_n1": info["log2_n1"], "rotating_copies": R,
+                   "streams": n_streams},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "step_hbm_frac": round(step_frac, 4),
@@ -382,8 +417,11 @@ def main() -> int:
         "p50_ms": round(float(np.percentile(r["per"], 50)), 5),
         "p99_ms": round(float(np.percentile(r["per"], 99)), 5),
         "plain_value": round(n_limb_ntts / (r["plain_ms"] * 1e-3), 1),
+        "single_stream_value": round(n_limb_ntts / (r["ms1"] * 1e-3), 1),
+        "single_stream_ms_per_step": round(r["ms1"], 5),
         "kernel_us": {k: round(v * 1e3, 2) for k, v in r["kms"].items()},
         "modes_us_per_step": {m: round(results[m]["ms"] * 1e3, 2) for m in results},
+        "modes_us_per_step_one_stream": {m: round(results[m]["ms1"] * 1e3, 2) for m in results},
         "roundtrip_ok": r["roundtrip_ok"],
         "autotune": tuned,
         "plan_create_ms": plan_ms,
