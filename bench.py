@@ -469,8 +469,9 @@ def polymul_profile_run(args) -> int:
 def polymul_bench(args):
     """Negacyclic products at N = 2^17, L = 60: c = a * b for 2-polynomial operands a and b
     (a ciphertext pair: forward NTT of a and of b, element-wise product, inverse NTT), with
-    table and OT twiddles.  Reports time per product, the twiddle bytes each plan reads per
-    product, and checks the product against the oracle."""
+    table and OT twiddles.  Reports time per product on one stream and for independent
+    products issued over --streams streams, the twiddle bytes each plan reads per product, and
+    checks every product against the oracle."""
     import torch
     import oracle
     import synth
@@ -490,6 +491,7 @@ def polymul_bench(args):
     if not args.no_tune:
         modes["tuned"] = tune_shape(N, primes, P)["opts"]
     steps = max(5, min(args.steps, 50))
+    S = max(1, args.streams)
     want = None
     for name, opts in modes.items():
         plan = ntt.ntt_plan_create(N, primes, **opts)
@@ -509,6 +511,31 @@ def polymul_bench(args):
             want = oracle.polymul(host[:P], host[P:], primes, oracle.roots(primes, N),
                                   max(1, min(16, os.cpu_count() or 1)))
         ok = bool(np.array_equal(dc.cpu().numpy().view(np.uint64), want))
+        # independent products round-robin over streams (product i on stream i mod S, into its
+        # own output; a and b are only read), as the headline's steps
+        ms_s = None
+        if S > 1:
+            cs = [torch.empty_like(da) for _ in range(S)]
+            sts = [torch.cuda.Stream() for _ in range(S)]
+            step_s = lambda i: ntt.ntt_polymul_negacyclic(plan, da, db, cs[i % S], None, sts[i % S])
+            ramp(step_s, args.ramp_ms)
+            torch.cuda.synchronize()
+            main_st = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(main_st)
+            for st in sts:
+                st.wait_event(e0)
+            for i in range(steps):
+                step_s(i)
+            for st in sts:
+                done = torch.cuda.Event()
+                done.record(st)
+                main_st.wait_event(done)
+            e1.record(main_st)
+            torch.cuda.synchronize()
+            ms_s = e0.elapsed_time(e1) / steps
+            ok = ok and all(bool(np.array_equal(c.cpu().numpy().view(np.uint64), want)) for c in cs)
+            del cs
         # twiddle bytes read per product: forward column and row passes of a and of b, the
         # fused rows (forward and inverse row twiddles) and the inverse column pass
         n1 = info["log2_n1"]
@@ -518,8 +545,12 @@ def polymul_bench(args):
         out[name] = {"plan": variant_key(info, ots), "ms_per_product": round(ms, 4),
                      "limb_ntts_per_s": round(limb_ntts / (ms * 1e-3), 1),
                      "twiddle_mb_per_product": round(tw / 1e6, 2), "matches_oracle": ok}
+        if ms_s is not None:
+            out[name].update({"streams": S, "ms_per_product_streams": round(ms_s, 4),
+                              "limb_ntts_per_s_streams": round(limb_ntts / (ms_s * 1e-3), 1)})
         log(f"[polymul {name}] {ms:.3f} ms/product  {limb_ntts / ms / 1e3:.3f} M limb-NTTs/s  "
-            f"twiddles {tw / 1e6:.1f} MB/product  oracle={'ok' if ok else 'MISMATCH'}")
+            + (f"({ms_s:.3f} ms over {S} streams)  " if ms_s is not None else "")
+            + f"twiddles {tw / 1e6:.1f} MB/product  oracle={'ok' if ok else 'MISMATCH'}")
         plan.destroy()
     del da, db, dc
     torch.cuda.empty_cache()

@@ -392,6 +392,37 @@ def test_plan_reuse_across_streams():
         plan.destroy()
 
 
+def test_round_robin_steps_on_two_streams():
+    """The bench's schedule: independent forward + inverse steps over copies, step i on stream
+    i mod 2 with no wait between steps; every copy ends as it started, and a forward run on one
+    stream while the other keeps stepping matches the oracle."""
+    N, L, P = 1 << 16, 6, 2
+    primes, psis, data = make(N, L, P, 60, 810)
+    plan = ntt.ntt_plan_create(N, primes, log2_n1=6, col_width=32)
+    try:
+        want = oracle.forward(data, primes, psis, THREADS)
+        sts = [torch.cuda.Stream(), torch.cuda.Stream()]
+        copies = [dev(data) for _ in range(6)]
+        torch.cuda.synchronize()
+        for i in range(24):
+            st = sts[i % 2]
+            ntt.ntt_forward(plan, copies[i % 6], stream=st)
+            ntt.ntt_inverse(plan, copies[i % 6], stream=st)
+        fwd = dev(data)
+        torch.cuda.synchronize()
+        for i in range(8):
+            ntt.ntt_forward(plan, copies[2 * i % 6 + 1], stream=sts[1])
+            ntt.ntt_inverse(plan, copies[2 * i % 6 + 1], stream=sts[1])
+            if i == 3:
+                ntt.ntt_forward(plan, fwd, stream=sts[0])
+        torch.cuda.synchronize()
+        for c in copies:
+            assert np.array_equal(host(c), data)
+        assert np.array_equal(host(fwd), want)
+    finally:
+        plan.destroy()
+
+
 # ------------------------------------------------------------------ batches of uneven jobs
 
 @pytest.mark.parametrize("mode", ["plain", "grouped", "graph", "branched"])
