@@ -25,6 +25,7 @@ __all__ = [
     "PATH_RADIX2", "PATH_REGISTER", "ntt_plan_log2_radix", "ntt_forward_u32", "ntt_inverse_u32",
     "ntt_pointwise_mul_u32", "ntt_polymul_negacyclic_u32", "ntt_plan_word_bits", "ntt_crt_words",
     "ntt_rns_decompose", "ntt_crt_reconstruct", "ntt_polymul_negacyclic_noalloc", "ntt_polymul_noalloc_max_words",
+    "ntt_device_copy",
 ]
 
 TWIDDLE_AUTO, TWIDDLE_TABLE, TWIDDLE_OT = 0, 1, 2
@@ -132,6 +133,8 @@ _lib.ntt_batch_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_Job), _u3
 _lib.ntt_batch_run.argtypes = [_vp, ctypes.c_int32, _vp]
 _lib.ntt_batch_assign.argtypes = [_vp, ctypes.POINTER(_Job), _u32, _vp]
 _lib.ntt_batch_destroy.argtypes = [_vp]
+_lib.ntt_device_copy.argtypes = [_vp, _vp, ctypes.c_size_t, _vp]
+_lib.ntt_device_copy.restype = ctypes.c_int
 _lib.ntt_status_string.argtypes = [ctypes.c_int]
 _lib.ntt_status_string.restype = ctypes.c_char_p
 _lib.ntt_last_error.argtypes = []
@@ -152,6 +155,20 @@ class NttError(RuntimeError):
 def _check(status: int, where: str) -> None:
     if status != 0:
         raise NttError(status, where)
+
+
+def ntt_device_copy(dst, src, stream=None) -> None:
+    """Copy tensor `src` into `dst` (same byte size, a multiple of 16) with the library's
+    one-pass copy kernel: the memory-rate yardstick of the measurements, not part of the
+    transform."""
+    for t, w in ((dst, "dst"), (src, "src")):
+        if not getattr(t, "is_cuda", False) or not t.is_contiguous():
+            raise ValueError(f"{w} must be a contiguous tensor in GPU memory")
+    nbytes = dst.numel() * dst.element_size()
+    if src.numel() * src.element_size() != nbytes:
+        raise ValueError("dst and src differ in size")
+    _check(_lib.ntt_device_copy(int(dst.data_ptr()), int(src.data_ptr()), nbytes, _stream(stream)),
+           "ntt_device_copy")
 
 
 def ntt_status_string(status: int) -> str:

@@ -19,7 +19,7 @@ LIB = os.environ.get("NTT_BUILD_OUT") or os.path.join(HERE, "libntt_mi355x.so")
 SOURCES = ["kernels_fwd_fast.hip", "kernels_inv_fast.hip", "kernels_fwd_wide.hip", "kernels_inv_wide.hip",
            "kernels_mul_fast.hip", "kernels_mul_wide.hip",
            "fused_fwd.hip", "fused_inv.hip", "kernels.hip", "permute.hip", "stages.hip", "kernels32.hip", "crt.hip",
-           "capi.cpp"]
+           "calib.hip", "capi.cpp"]
 # (object name, source, defines): the row-pass instances, one unit per direction (forward,
 # inverse, key product), arithmetic policy and range of row lengths
 ROW_RANGES = ((1, 7), (8, 10), (11, 13))
@@ -42,6 +42,8 @@ FLAGS = [
 # Host-only sources: they decide which launches happen but hold no device code, so a change
 # there leaves every kernel's measured time (and the counters taken of it) valid.
 HOST_ONLY_SOURCES = ("capi.cpp", "plan_math.hpp", "plan_life.hpp", "tune_file.hpp", "crt_math.hpp")
+# Device code that no plan launches (the calibration copy): outside the hash as well.
+UNHASHED_DEVICE_SOURCES = ("calib.hip",)
 
 
 def source_hash() -> str:
@@ -51,7 +53,7 @@ def source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
     for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".hpp")) and name not in HOST_ONLY_SOURCES:
+        if name.endswith((".hip", ".hpp")) and name not in HOST_ONLY_SOURCES + UNHASHED_DEVICE_SOURCES:
             with open(os.path.join(CSRC, name), "rb") as f:
                 h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]

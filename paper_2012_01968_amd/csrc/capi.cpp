@@ -941,6 +941,11 @@ static ntt_status upload_batch(ntt_batch_s* b, const std::vector<nttk::VecDesc>&
   return NTT_OK;
 }
 
+namespace nttk {
+// One-pass device copy of n16 16-byte vectors (calib.hip).
+hipError_t launch_copy16(const void* src, void* dst, uint64_t n16, hipStream_t st);
+}  // namespace nttk
+
 extern "C" {
 
 ntt_status ntt_plan_create(ntt_plan_t* out, uint32_t N, const uint64_t* primes, uint32_t L,
@@ -1102,6 +1107,21 @@ ntt_status ntt_inverse(ntt_plan_t plan, uint64_t* d_data, uint32_t n_polys, void
     return e == hipSuccess ? NTT_OK : hip_fail(e, "ntt_inverse launch");
   } catch (...) {
     return fail(NTT_ERR_ARG, "unexpected failure in ntt_inverse");
+  }
+}
+
+ntt_status ntt_device_copy(void* d_dst, const void* d_src, size_t bytes, void* stream) {
+  try {
+    if (bytes == 0) return NTT_OK;
+    if (!d_dst || !d_src) return fail(NTT_ERR_ARG, "null buffer");
+    if (((uintptr_t)d_dst | (uintptr_t)d_src) % 16 != 0) return fail(NTT_ERR_ARG, "buffers must be 16-byte aligned");
+    if (bytes % 16 != 0 || bytes >= ((size_t)1 << 36)) return fail(NTT_ERR_ARG, "bytes must be a multiple of 16 below 2^36");
+    const uintptr_t a = (uintptr_t)d_dst, b = (uintptr_t)d_src;
+    if (a < b + bytes && b < a + bytes) return fail(NTT_ERR_ARG, "buffers overlap");
+    const hipError_t e = nttk::launch_copy16(d_src, d_dst, bytes / 16, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? NTT_OK : hip_fail(e, "ntt_device_copy launch");
+  } catch (...) {
+    return fail(NTT_ERR_ARG, "unexpected failure in ntt_device_copy");
   }
 }
 

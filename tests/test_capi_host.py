@@ -124,6 +124,19 @@ def test_argument_errors_are_synchronous(lib):
     assert lib.ntt_forward(None, None, 1, None) == -1
 
 
+def test_device_copy_argument_errors(lib):
+    vp = ctypes.c_void_p
+    lib.ntt_device_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    lib.ntt_device_copy.restype = ctypes.c_int
+    assert lib.ntt_device_copy(None, None, 0, None) == 0              # nothing to copy
+    assert lib.ntt_device_copy(None, 4096, 64, None) == -1            # null destination
+    assert lib.ntt_device_copy(8192, None, 64, None) == -1            # null source
+    assert lib.ntt_device_copy(8200, 4096, 64, None) == -1            # misaligned
+    assert lib.ntt_device_copy(8192, 4096, 40, None) == -1            # not a multiple of 16
+    assert lib.ntt_device_copy(8192, 4096, 1 << 36, None) == -1       # too large
+    assert lib.ntt_device_copy(4096 + 32, 4096, 64, None) == -1       # overlapping
+
+
 def test_batch_argument_errors(lib):
     vp = ctypes.c_void_p
     lib.ntt_batch_create.argtypes = [ctypes.POINTER(vp), vp, ctypes.c_uint32]

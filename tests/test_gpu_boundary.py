@@ -4,7 +4,8 @@
   (and only for it), and is freed when the batch lets go;
 * products on several streams of one plan each use their own scratch and all match the
   oracle, also when they run at the same time and when one stream's scratch grows;
-* use_autotune=1 takes the tuner's file entry for a cached shape.
+* use_autotune=1 takes the tuner's file entry for a cached shape;
+* the measurement's yardstick copy (ntt_device_copy) moves every byte.
 
 Every result is compared with the CPU oracle, element by element.
 """
@@ -158,3 +159,13 @@ def test_use_autotune_takes_the_cached_choice():
         assert not ntt.ntt_plan_tuned(small)
     finally:
         small.destroy()
+
+
+def test_device_copy():
+    """The measurement's yardstick copy moves every byte, at sizes that leave a partial block."""
+    for n in (2, 4096 * 2 + 6, 47185920 // 8):
+        src = torch.randint(-(1 << 62), 1 << 62, (n,), dtype=torch.int64, device="cuda")
+        dst = torch.zeros_like(src)
+        ntt.ntt_device_copy(dst, src)
+        torch.cuda.synchronize()
+        assert torch.equal(dst, src)
