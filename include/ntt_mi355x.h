@@ -358,7 +358,7 @@ ntt_status ntt_crt_reconstruct(ntt_plan_t plan, const uint64_t* d_res, uint64_t*
  * Not part of the transform: a plain device-to-device copy of `bytes` bytes on the current
  * device, one 16-byte vector per lane in a single pass, which measurements use as the memory
  * rate a kernel on this GPU can reach to compare the passes with.  `bytes` must be a multiple
- * of 16 and below 2^36; both pointers 16-byte aligned device addresses of caller-owned,
+ * of 16 and below 2^35; both pointers 16-byte aligned device addresses of caller-owned,
  * non-overlapping buffers.  Enqueued on `stream`; NTT_ERR_ARG for null or misaligned pointers
  * and bad sizes (0 bytes is a no-op), NTT_ERR_HIP for a launch failure. */
 ntt_status ntt_device_copy(void* d_dst, const void* d_src, size_t bytes, void* stream);

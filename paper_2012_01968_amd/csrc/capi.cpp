@@ -1115,7 +1115,7 @@ ntt_status ntt_device_copy(void* d_dst, const void* d_src, size_t bytes, void* s
     if (bytes == 0) return NTT_OK;
     if (!d_dst || !d_src) return fail(NTT_ERR_ARG, "null buffer");
     if (((uintptr_t)d_dst | (uintptr_t)d_src) % 16 != 0) return fail(NTT_ERR_ARG, "buffers must be 16-byte aligned");
-    if (bytes % 16 != 0 || bytes >= ((size_t)1 << 36)) return fail(NTT_ERR_ARG, "bytes must be a multiple of 16 below 2^36");
+    if (bytes % 16 != 0 || bytes >= ((size_t)1 << 35)) return fail(NTT_ERR_ARG, "bytes must be a multiple of 16 below 2^35");
     const uintptr_t a = (uintptr_t)d_dst, b = (uintptr_t)d_src;
     if (a < b + bytes && b < a + bytes) return fail(NTT_ERR_ARG, "buffers overlap");
     const hipError_t e = nttk::launch_copy16(d_src, d_dst, bytes / 16, static_cast<hipStream_t>(stream));

@@ -133,7 +133,7 @@ def test_device_copy_argument_errors(lib):
     assert lib.ntt_device_copy(8192, None, 64, None) == -1            # null source
     assert lib.ntt_device_copy(8200, 4096, 64, None) == -1            # misaligned
     assert lib.ntt_device_copy(8192, 4096, 40, None) == -1            # not a multiple of 16
-    assert lib.ntt_device_copy(8192, 4096, 1 << 36, None) == -1       # too large
+    assert lib.ntt_device_copy(8192, 4096, 1 << 35, None) == -1       # too large
     assert lib.ntt_device_copy(4096 + 32, 4096, 64, None) == -1       # overlapping
 
 
