@@ -585,8 +585,9 @@ UNEVEN = dict(polys=256, logNs=(13, 14, 15, 16, 17), weights=(0.1, 0.2, 0.3, 0.3
 
 def uneven_batch_bench(args):
     """256 independent polynomials of uneven N and limb count, forward then inverse NTT
-    each, as one batch: one plain call sequence per polynomial, grouped launches, and the
-    grouped launches replayed from a captured hipGraph."""
+    each, as one batch: one plain call sequence per polynomial, grouped launches, the grouped
+    launches replayed from a captured hipGraph (sequential or branched), and steps replayed
+    over --streams streams from batches of their own copies."""
     import torch
     import synth
     import paper_2012_01968_amd as ntt
@@ -643,7 +644,42 @@ def uneven_batch_bench(args):
                      "p50_ms": round(float(np.percentile(per, 50)), 4),
                      "p99_ms": round(float(np.percentile(per, 99)), 4)}
         log(f"[uneven {name}] {ms:.3f} ms/step  {limb_ntts / ms / 1e3:.3f} M limb-NTTs/s")
-    ok = all(torch.equal(b, src[k][:L]) for b, k, L in zip(bufs, logNs.tolist(), Ls.tolist()))
+    # independent steps over two streams, as the headline's: a second batch of the same jobs on
+    # copies of their own, and step i replays batch i mod 2's graph on stream i mod 2
+    S = max(1, args.streams)
+    if S > 1:
+        extra = []
+        for _ in range(S - 1):
+            bufs_s = [b.clone() for b in bufs]
+            extra.append((bufs_s, ntt.ntt_batch_create(
+                [(j[0], b, j[2], j[3], j[4]) for j, b in zip(jobs, bufs_s)])))
+        batches = [batch] + [bt for _, bt in extra]
+        sts = [torch.cuda.Stream() for _ in range(S)]
+        step_s = lambda i: ntt.ntt_batch_run(batches[i % S], ntt.BATCH_GRAPH, sts[i % S])
+        ramp(step_s, args.ramp_ms)
+        torch.cuda.synchronize()
+        main_st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(main_st)
+        for st in sts:
+            st.wait_event(e0)
+        for i in range(steps):
+            step_s(i)
+        for st in sts:
+            done = torch.cuda.Event()
+            done.record(st)
+            main_st.wait_event(done)
+        e1.record(main_st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out["graph_streams"] = {"streams": S, "ms_per_step": round(ms, 4),
+                                "limb_ntts_per_s": round(limb_ntts / (ms * 1e-3), 1)}
+        log(f"[uneven graph over {S} streams] {ms:.3f} ms/step  {limb_ntts / ms / 1e3:.3f} M limb-NTTs/s")
+        for bufs_s, bt in extra:
+            bufs = bufs + bufs_s
+            bt.destroy()
+    ok = all(torch.equal(b, src[k][:L]) for b, k, L in
+             zip(bufs, logNs.tolist() * (len(bufs) // len(logNs)), Ls.tolist() * (len(bufs) // len(Ls))))
     out["roundtrip_ok"] = bool(ok)
     out["matches_oracle"] = uneven_forward_matches_oracle(plans, src, chain, logNs, Ls, Lmax)
     log(f"[uneven] forward of all {cfg['polys']} polys (grouped and both graph runs) "
