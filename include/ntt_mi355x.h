@@ -87,9 +87,9 @@ typedef struct {
 /* Tile options (r1, wg_size, col_width; Section VI-C's per-thread NTT size and thread-block
  * shape) apply to 64-bit plans on the split path; elsewhere they are refused with
  * NTT_ERR_UNSUPPORTED, as is r1 = 4 for rows of 8192 points (a row's lanes form one
- * workgroup of at most 1024) and a col_width wider than N2.  The row passes with a key
- * product (ntt_polymul_negacyclic, batches with NTT_OP_MULKEY) always run 8 values per lane.
- * Every tile shape computes the same residues; only the speed differs. */
+ * workgroup of at most 1024) and a col_width wider than N2.  The shape applies to every row
+ * pass of the plan, the key-product rows of ntt_polymul_negacyclic and NTT_OP_MULKEY batch
+ * jobs included.  Every tile shape computes the same residues; only the speed differs. */
 
 /* Slot order of the NTT domain (Section III-C).  BITREV (the default) is Algorithm 1's own
  * order: forward output slot i holds A_{brv(i)}, and the inverse takes that order.  NATURAL

@@ -598,18 +598,15 @@ __global__ __launch_bounds__((ColCfg<LOGM, WREQ>::NT)) void inv_col_kernel(PassA
 constexpr int row_t(int logm, int lr) { return (1 << logm) >> (lr < logm ? lr : logm); }
 constexpr int row_nth_canon(int logm, int lr, int nth) { return row_t(logm, lr) >= nth ? row_t(logm, lr) : nth; }
 
-// LR2: whether the 4-values-per-lane shapes are built for this kernel (see mul_rows_lm).
-template <int LOGM, bool LR2 = true, typename F>
+template <int LOGM, typename F>
 __host__ hipError_t with_row_shape(const PassArgs& a, F&& f) {
-  const int lr = (a.row_lr && LR2) ? (int)a.row_lr : row_lr(LOGM);
+  const int lr = a.row_lr ? (int)a.row_lr : row_lr(LOGM);
   const int nth = a.row_nth ? (int)a.row_nth : kRowThreads;
 #define NTTK_SHAPE(LR_, NTH_)                                                                             \
   if (lr == LR_ && nth == NTH_)                                                                           \
     return f(std::integral_constant<int, row_nth_canon(LOGM, LR_, NTH_)>{}, std::integral_constant<int, LR_>{});
   NTTK_SHAPE(3, 128) NTTK_SHAPE(3, 64) NTTK_SHAPE(3, 256)
-  if constexpr (LR2) {
-    NTTK_SHAPE(2, 128) NTTK_SHAPE(2, 64) NTTK_SHAPE(2, 256)
-  }
+  NTTK_SHAPE(2, 128) NTTK_SHAPE(2, 64) NTTK_SHAPE(2, 256)
 #undef NTTK_SHAPE
   return hipErrorInvalidValue;
 }
@@ -774,15 +771,9 @@ hipError_t go_mul_row(const PassArgs& af, const PassArgs& ai, hipStream_t st) {
   return hipGetLastError();
 }
 
-// The key-product rows run 8 values per lane whatever the plan's r1: at 4 values per lane,
-// 128-point rows with one OT stage gave wrong products on the GPU (forward and inverse row
-// passes of that shape are exact); the cause was not found, so that shape is not built.
-#ifndef NTTK_MUL_LR2
-#define NTTK_MUL_LR2 0
-#endif
 template <bool FAST, int LM>
 hipError_t mul_rows_lm(const PassArgs& af, const PassArgs& ai, int ots, bool scale0, hipStream_t st) {
-  return with_row_shape<LM, NTTK_MUL_LR2 != 0>(af, [&](auto nth, auto lr) {
+  return with_row_shape<LM>(af, [&](auto nth, auto lr) {
     constexpr int NTH = decltype(nth)::value, LRR = decltype(lr)::value;
     if (scale0) {
       if (ots == 0) return go_mul_row<FAST, LM, 0, true, NTH, LRR>(af, ai, st);

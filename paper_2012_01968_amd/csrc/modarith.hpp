@@ -89,16 +89,15 @@ __device__ __forceinline__ uint32_t add_u32(uint32_t a, uint32_t b) {
   return r;
 }
 
-// x - m when x >= m, else x; needs x < 2^63 and m < 2^63 (negm = 2^64 - m).  The sign of
-// x - m is spread to a mask and two bit-field selects pick the halves, which keeps the
-// select off the VCC path (no compare, no VALU-to-VCC hazard).
+// x - m when x >= m, else x; needs |x - m| < 2^63 (negm = 2^64 - m), so the sign of x - m
+// decides.  Written as a plain conditional: a 64-bit sign test and two conditional moves, as
+// many instructions as the mask-and-bit-field-select form (v_bfi_b32) it replaces.  With that
+// form (issued from inline asm, or kept by an empty asm statement on the mask) the key-product
+// row pass of 128-point rows with 4 values per lane and one OT stage computed wrong products
+// at N1 >= 256; with this one it is exact, like every other kernel.
 __device__ __forceinline__ uint64_t csub_sign(uint64_t x, uint64_t negm) {
   const uint64_t d = x + negm;
-  const uint32_t m = (uint32_t)((int32_t)(uint32_t)(d >> 32) >> 31);
-  uint32_t lo, hi;
-  asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(lo) : "v"(m), "v"((uint32_t)x), "v"((uint32_t)d));
-  asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(hi) : "v"(m), "v"((uint32_t)(x >> 32)), "v"((uint32_t)(d >> 32)));
-  return make_u64(lo, hi);
+  return (int64_t)d < 0 ? x : d;
 }
 
 template <bool FAST>
