@@ -48,3 +48,14 @@ def test_plan_names():
     assert b.variant_key({"kernel_path": 2, "log2_n1": 7}, 2) == "ot2-fused-n1=7"
     assert b.variant_key({"kernel_path": 1, "log2_n1": 6, "r1": 4, "wg_size": 0, "col_width": 32}, 1) == \
         "ot1-split-n1=6-r1=4-col_width=32"
+
+
+def test_bench_refuses_several_gpus():
+    """The measurement covers one GPU: --gpus above 1 exits with status 2 and says why, before
+    touching any device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "single MI355X" in r.stderr and r.stdout == ""
