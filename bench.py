@@ -294,9 +294,9 @@ def main() -> int:
             return ms, wall, per
 
         ms, wall, per = timed_steps(n_streams)
-        ms1 = ms
+        ms1, per1 = ms, per
         if n_streams > 1:
-            ms1, _, _ = timed_steps(1)
+            ms1, _, per1 = timed_steps(1)
 
         # per-kernel durations: each kernel launched back to back over K distinct rotating copies,
         # with events only around each run of K launches (an event between two kernels drains the
@@ -345,7 +345,7 @@ def main() -> int:
         plain_ms = pe0.elapsed_time(pe1) / args.steps
 
         ok = bool(torch.equal(bufs[0], dev0) and torch.equal(bufs[R - 1], dev0))
-        results[mode] = dict(plan=plan, info=info, npass=npass, ms=ms, ms1=ms1, per=per, wall=wall, kms=kms,
+        results[mode] = dict(plan=plan, info=info, npass=npass, ms=ms, ms1=ms1, per=per, per1=per1, wall=wall, kms=kms,
                              plain_ms=plain_ms, roundtrip_ok=ok)
         log(f"[{mode}] {ms*1e3:.1f} us/step over {n_streams} streams, {ms1*1e3:.1f} on one  "
             f"({180/ms*1e3/1e6:.3f} M NTTs/s)  kernels(us): "
@@ -440,6 +440,8 @@ def main() -> int:
         "plain_value": round(n_limb_ntts / (r["plain_ms"] * 1e-3), 1),
         "single_stream_value": round(n_limb_ntts / (r["ms1"] * 1e-3), 1),
         "single_stream_ms_per_step": round(r["ms1"], 5),
+        "single_stream_p50_ms": round(float(np.percentile(r["per1"], 50)), 5),
+        "single_stream_p99_ms": round(float(np.percentile(r["per1"], 99)), 5),
         "warm_same_buffer_ms_per_step": round(warm_ms, 5),
         "kernel_us": {k: round(v * 1e3, 2) for k, v in r["kms"].items()},
         "modes_us_per_step": {m: round(results[m]["ms"] * 1e3, 2) for m in results},
