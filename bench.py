@@ -294,9 +294,11 @@ def main() -> int:
             return ms, wall, per
 
         ms, wall, per = timed_steps(n_streams)
-        ms1, per1 = ms, per
+        ms_s, ms1, per1, used = ms, ms, per, n_streams
         if n_streams > 1:
             ms1, _, per1 = timed_steps(1)
+            if ms1 < ms:   # report the faster schedule (the streams' gain is measured, not assumed)
+                ms, per, used = ms1, per1, 1
 
         # per-kernel durations: each kernel launched back to back over K distinct rotating copies,
         # with events only around each run of K launches (an event between two kernels drains the
@@ -345,9 +347,10 @@ def main() -> int:
         plain_ms = pe0.elapsed_time(pe1) / args.steps
 
         ok = bool(torch.equal(bufs[0], dev0) and torch.equal(bufs[R - 1], dev0))
-        results[mode] = dict(plan=plan, info=info, npass=npass, ms=ms, ms1=ms1, per=per, per1=per1, wall=wall, kms=kms,
+        results[mode] = dict(plan=plan, info=info, npass=npass, ms=ms, ms1=ms1, per=per, per1=per1, used=used,
+                             wall=wall, kms=kms,
                              plain_ms=plain_ms, roundtrip_ok=ok)
-        log(f"[{mode}] {ms*1e3:.1f} us/step over {n_streams} streams, {ms1*1e3:.1f} on one  "
+        log(f"[{mode}] {ms_s*1e3:.1f} us/step over {n_streams} streams, {ms1*1e3:.1f} on one  "
             f"({180/ms*1e3/1e6:.3f} M NTTs/s)  kernels(us): "
             + ", ".join(f"{k}={v*1e3:.1f}" for k, v in kms.items())
             + f"  plain {plain_ms*1e3:.1f} us/step  roundtrip_ok={ok}")
@@ -430,7 +433,7 @@ def main() -> int:
                                "forward NTT then inverse NTT (180 limb-NTTs per step)",
                    "N": N, "L": L, "polys": P, "variant": best, "plan": variant_key(info, ots),
                    "ot_stages": ots, "log2_n1": info["log2_n1"], "rotating_copies": R,
-                   "streams": n_streams},
+                   "streams": r["used"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "step_hbm_frac": round(step_frac, 4),
