@@ -170,3 +170,29 @@ def test_debug_modes_change_nothing(mode, monkeypatch):
                     assert np.array_equal(host(c), want_m), f"{mode} N=2^{logN} {opts}: product"
                 finally:
                     plan.destroy()
+
+
+@pytest.mark.parametrize("mode", ["", "poison", "reverse"])
+def test_key_product_rows_of_128_points(mode, monkeypatch):
+    """Products whose row passes are 128 points at 4 values per lane (32 lanes, two rows per
+    wave) with one OT stage, for every N1 from 2^6 to 2^10 and every row workgroup size, plus
+    the 8-value and two-stage neighbours, in each debug mode.  This is the shape that an
+    earlier form of the conditional subtraction computed wrongly at N1 >= 2^8."""
+    monkeypatch.setenv("NTT_DEBUG", mode)
+    for logN in (13, 14, 15, 16, 17):
+        N, n1 = 1 << logN, logN - 7
+        primes = synth.gen_primes(5000 + logN, N, 60, L)
+        psis = oracle.roots(primes, N)
+        a = synth.residue_batch(5000 + logN, primes, N, P)
+        b = synth.residue_batch(5001 + logN, primes, N, P)
+        want = oracle.polymul(a, b, primes, psis, THREADS)
+        for r1, wg, ots in ((4, 128, 1), (4, 64, 1), (4, 256, 1), (8, 128, 1), (4, 128, 2)):
+            plan = ntt.ntt_plan_create(N, primes, log2_n1=n1, kernel_path=ntt.PATH_SPLIT, r1=r1, wg_size=wg,
+                                       twiddle_mode=ntt.TWIDDLE_OT, ot_stages=ots, ot_log2_base=10)
+            try:
+                c = torch.empty_like(dev(a))
+                ntt.ntt_polymul_negacyclic(plan, dev(a), dev(b), c)
+                torch.cuda.synchronize()
+                assert np.array_equal(host(c), want), f"N=2^{logN} n1={n1} r1={r1} wg={wg} ots={ots} {mode}"
+            finally:
+                plan.destroy()
