@@ -430,7 +430,8 @@ def main() -> int:
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": "one ciphertext, N=2^16, L=45 primes in [2^59,2^60) (seed 2), 2 polys, "
-                               "forward NTT then inverse NTT (180 limb-NTTs per step)",
+                               "forward NTT then inverse NTT (180 limb-NTTs per step); independent steps over "
+                               "rotating copies, issued round-robin on `streams` streams",
                    "N": N, "L": L, "polys": P, "variant": best, "plan": variant_key(info, ots),
                    "ot_stages": ots, "log2_n1": info["log2_n1"], "rotating_copies": R,
                    "streams": r["used"]},
